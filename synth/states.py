@@ -1,0 +1,45 @@
+"""Seeded thermochemical states and Newton inputs.
+
+State layout matches the library's: phi[j, s] with j = 0 the temperature and
+j = 1..N-1 the mass fractions Y_1..Y_{N-1} (the last species' mass fraction is
+implied), p[s] in Pa; the state index is the fastest-varying one.
+"""
+from __future__ import annotations
+
+from typing import Tuple
+
+import numpy as np
+
+from .mechgen import ATM, CONFIGS, STATE_SEED_BASE
+
+NEWTON_GAMMA = 0.4358665
+
+
+def draw_states(seed: int, n_species: int, n_states: int, T=(800.0, 2200.0),
+                P_atm=(1.0, 50.0), dirichlet=0.3) -> Tuple[np.ndarray, np.ndarray]:
+    """T ~ U[T], p ~ U[P_atm] atm, Y ~ Dirichlet(alpha) over all N species."""
+    rng = np.random.default_rng(seed)
+    T_s = rng.uniform(T[0], T[1], size=n_states)
+    p_s = rng.uniform(P_atm[0], P_atm[1], size=n_states) * ATM
+    Y = rng.dirichlet(np.full(n_species, dirichlet), size=n_states)  # (S, N)
+    phi = np.empty((n_species, n_states), dtype=np.float64)
+    phi[0] = T_s
+    phi[1:] = Y[:, : n_species - 1].T
+    return np.ascontiguousarray(phi), p_s
+
+
+def config_states(cfg_id: int, n_states: int | None = None):
+    c = CONFIGS[cfg_id]
+    n = c["n_states"] if n_states is None else n_states
+    return draw_states(STATE_SEED_BASE + cfg_id, c["n_species"], n, c["T"],
+                       c["P_atm"], c["dirichlet"])
+
+
+def draw_newton_inputs(seed: int, n_species: int, n_states: int,
+                       h_range=(1e-9, 1e-5)):
+    """Per-state step size h (log-uniform) and right-hand side b ~ N(0, 1),
+    b laid out [N][n_states]."""
+    rng = np.random.default_rng(seed)
+    h = np.exp(rng.uniform(np.log(h_range[0]), np.log(h_range[1]), size=n_states))
+    rhs = rng.standard_normal((n_species, n_states))
+    return h, np.ascontiguousarray(rhs)
