@@ -256,9 +256,11 @@ def _make_species(rng, elements, bounds, n_species, inert_last="N2",
         comps.append({e: comp.get(e, 0) for e in elements})
         return True
 
-    n_reactive = n_species - (0 if reactive_last else 1)
-    if "Ar" in elements and not reactive_last:
-        n_reactive -= 1
+    n_reactive = n_species
+    if not reactive_last:
+        n_reactive -= 1                              # inert last species
+        if "Ar" in elements and "N" in elements:
+            n_reactive -= 1                          # an extra inert Ar
     # atoms first, then a few diatomics, then random compositions in the box
     for e in reactive_elems:
         if bounds.get(e, 0) >= 1 and len(comps) < n_reactive:
@@ -286,6 +288,8 @@ def _make_species(rng, elements, bounds, n_species, inert_last="N2",
             lo, hi = _fit_nasa(rng, 1)
             species.append(Species(_species_name(comp, taken), comp,
                                    ATOMIC_WEIGHTS["Ar"], 1000.0, lo, hi, inert=True))
+        if "N" not in elements:       # Ar (appended above) is the inert last species
+            return species
         comp = {e: 0 for e in elements}
         comp["N"] = 2
         lo, hi = _fit_nasa(rng, 2)
@@ -469,6 +473,9 @@ def make_mechanism(seed: int, n_species: int, n_reactions: int,
     """Build a random element-balanced mechanism with the given reaction mix."""
     assert sum(mix.values()) == n_reactions, (mix, n_reactions)
     rng = np.random.default_rng(seed)
+    elements = list(elements)
+    if not reactive_last and "N" not in elements and "Ar" not in elements:
+        elements.append("Ar")
     species = _make_species(rng, list(elements), bounds, n_species,
                             reactive_last=reactive_last)
     bal = _Balancer(species, list(elements))
