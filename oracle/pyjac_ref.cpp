@@ -102,6 +102,9 @@ struct Mech {
   std::vector<std::array<double, 7>> lo, hi;
   std::vector<Rxn> rxn;
   std::vector<int> nu_f, nu_r;    // dense N x NR, [k * NR + i]
+  // index lists that only skip zero stoichiometric terms of the sums below
+  std::vector<std::vector<int>> rxn_species;   // species with nu' or nu'' != 0, ascending
+  std::vector<std::vector<int>> species_rxns;  // reactions with nu_ki != 0, ascending
   int nuf(int k, int i) const { return nu_f[(size_t)k * NR + i]; }
   int nur(int k, int i) const { return nu_r[(size_t)k * NR + i]; }
   int nu(int k, int i) const { return nur(k, i) - nuf(k, i); }
@@ -258,6 +261,13 @@ Mech parse(const std::string& text) {
     m.rxn.push_back(r);
   }
   tk.expect("end");
+  m.rxn_species.assign(m.NR, {});
+  m.species_rxns.assign(m.N, {});
+  for (int i = 0; i < m.NR; ++i)
+    for (int k = 0; k < m.N; ++k) {
+      if (m.nuf(k, i) || m.nur(k, i)) m.rxn_species[i].push_back(k);
+      if (m.nu(k, i)) m.species_rxns[k].push_back(i);
+    }
   return m;
 }
 
@@ -418,7 +428,7 @@ template <class S> void reaction_values(const Mech& m, int i, const State<S>& st
   if (r.rev == KC) {
     int dnu = 0;
     S sum = S(0);
-    for (int k = 0; k < m.N; ++k) {
+    for (int k : m.rxn_species[i]) {
       int n = m.nu(k, i);
       if (n) { dnu += n; sum += S(n) * (st.sR[k] - st.hRT[k]); }
     }
@@ -451,7 +461,7 @@ template <class S> void rhs(const Mech& m, const S& T, double p, const S* y, S* 
   }
   for (int k = 0; k < N; ++k) {
     S acc = S(0);
-    for (int i = 0; i < m.NR; ++i) { int n = m.nu(k, i); if (n) acc += S(n) * q[i]; }
+    for (int i : m.species_rxns[k]) acc += S(m.nu(k, i)) * q[i];
     wdot[k] = acc;
   }
   S hsum = S(0);
@@ -533,7 +543,7 @@ void jacobian(const Mech& m, double T, double p, const double* y, double* J /* N
     double dkrdT = 0;
     if (r.rev == KC) {
       double snu = 0;
-      for (int k = 0; k < N; ++k) { int n = m.nu(k, i); if (n) snu += n * dBdT[k]; }
+      for (int k : m.rxn_species[i]) { int n = m.nu(k, i); if (n) snu += n * dBdT[k]; }
       dkrdT = x.kr * (dkfdT / x.kf - snu);                               // Eq. (dkrdT_general) with dK_c/dT
     } else if (r.rev == EXPLICIT) dkrdT = x.kr / T * (r.revarr.b + r.revarr.Ta / T);
     // --- dR/dT: product rule with d[X]/dT = -[X]/T (Eqs. dRfdT-orig, dRdT_explicit_rev_general)
@@ -592,9 +602,8 @@ void jacobian(const Mech& m, double T, double p, const double* y, double* J /* N
       }
       // dR_i/dY_j: product rule over every species of the reaction (Sec. 3.1, reversible form)
       double acc = 0;
-      for (int k = 0; k < N; ++k) {
+      for (int k : m.rxn_species[i]) {
         int a = m.nuf(k, i), b = m.nur(k, i);
-        if (!a && !b) continue;
         double dkj = (k == j) ? 1.0 : 0.0, dkN = (k == N - 1) ? 1.0 : 0.0;
         if (a) {
           double other = 1;
@@ -612,25 +621,23 @@ void jacobian(const Mech& m, double T, double p, const double* y, double* J /* N
   }
   for (int k = 0; k < N; ++k) {
     double acc = 0;
-    for (int i = 0; i < NR; ++i) { int n = m.nu(k, i); if (n) acc += n * vals[i].c * (vals[i].Rf - vals[i].Rr); }
+    for (int i : m.species_rxns[k]) acc += m.nu(k, i) * vals[i].c * (vals[i].Rf - vals[i].Rr);
     wdot[k] = acc;
   }
   // Species rows k = 1..N (row N is the placeholder for the last species), Eqs. (jac_dydt), (jac_dydy)
   std::vector<double> JT(N), JY((size_t)N * (N - 1));
   for (int k = 0; k < N; ++k) {
     double acc = 0;
-    for (int i = 0; i < NR; ++i) {
+    for (int i : m.species_rxns[k]) {
       int n = m.nu(k, i);
-      if (!n) continue;
       const auto& x = vals[i];
       acc += n * (dcdT[i] * (x.Rf - x.Rr) + x.c * (dRdT[i] + (x.Rf - x.Rr) / T));
     }
     JT[k] = m.W[k] / rho * acc;
     for (int j = 0; j < N - 1; ++j) {
       double s = 0;
-      for (int i = 0; i < NR; ++i) {
+      for (int i : m.species_rxns[k]) {
         int n = m.nu(k, i);
-        if (!n) continue;
         const auto& x = vals[i];
         s += n * (dcdY[(size_t)i * (N - 1) + j] * (x.Rf - x.Rr) + x.c * dRdY[(size_t)i * (N - 1) + j]);
       }
