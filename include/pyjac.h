@@ -1,0 +1,160 @@
+/*
+ * pyjac.h -- C ABI of libpyjac_mi355x.so, an MI355X (gfx950) library for the
+ * data-parallel hot path of the analytical chemical-kinetics Jacobian of
+ * Niemeyer, Curtis & Sung, "pyJac: analytical Jacobian generator for chemical
+ * kinetics" (arXiv:1605.03262): reaction rates, species production rates, the
+ * constant-pressure ideal-gas source terms and their dense analytical Jacobian,
+ * evaluated for very many independent thermochemical states, plus a batched
+ * solve of the Newton matrix I - h*gamma*J.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Units are SI with kmol: T [K], p [Pa], Y [-], t [s], concentrations
+ *    [kmol/m^3], rates of progress [kmol/(m^3 s)].  All floating point is FP64
+ *    unless stated.
+ *  - State vector (Sec. 2.1, Eq. vars): Phi = {T, Y_1, ..., Y_{N-1}}; the last
+ *    species' mass fraction is Y_N = 1 - sum Y_k (Eq. y_nsp) and is not stored.
+ *  - Layout: every per-state array is element-major with the state index
+ *    fastest: element e of state s lives at ptr[e*ld + s], ld >= n_states.
+ *      phi  [N][ld]        e = 0 is T, e = j (1..N-1) is Y_j
+ *      p    [ld]           pressure, held constant (Sec. 2.1 footnote)
+ *      jac  [N*N][ld]      e = i*N + j holds J_ij = d f_i / d Phi_j (Sec. 3.1)
+ *  - Array arguments of the evaluation calls are DEVICE pointers owned by the
+ *    caller (e.g. a torch tensor's data_ptr()).  Every double pointer must be
+ *    8-byte aligned.
+ *  - stream is a hipStream_t passed as void*; NULL means the default stream.
+ *    Evaluation calls only enqueue work and return; results are ready when the
+ *    stream reaches that point.  Argument errors are reported synchronously
+ *    and nothing is enqueued; a failed launch returns PYJAC_E_DEVICE.
+ *  - Numerical trouble in a state (non-finite inputs, T outside the thermo
+ *    fits, a singular Newton matrix) never fails a call: it shows up as
+ *    non-finite outputs or in the per-state info array.
+ *  - The result for a state depends only on that state's inputs and the
+ *    mechanism: never on n_states, ld, the stream or other states in the
+ *    batch (no atomics, fixed reduction order).
+ *  - A const pyjac_mech* may be used concurrently from many host threads and
+ *    streams; pyjac_mech_free must not race with calls using the handle.
+ *  - pyjac_last_error() returns a thread-local message for the most recent
+ *    failing call on the calling thread.
+ */
+#ifndef PYJAC_MI355X_H
+#define PYJAC_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pyjac_mech pyjac_mech;   /* opaque; owns device-resident tables */
+typedef int32_t pyjac_status;
+
+#define PYJAC_OK              0
+#define PYJAC_E_INVALID      -1   /* bad argument (NULL, negative size, ld < n, misaligned) */
+#define PYJAC_E_PARSE        -2   /* malformed mechanism text */
+#define PYJAC_E_UNSUPPORTED  -3   /* feature outside the supported set */
+#define PYJAC_E_DEVICE       -4   /* HIP runtime or launch failure */
+#define PYJAC_E_NOMEM        -5   /* device or host allocation failed */
+#define PYJAC_E_IO           -6   /* file could not be read */
+#define PYJAC_E_UNBALANCED   -7   /* a reaction does not conserve elements */
+#define PYJAC_E_WORKSPACE    -8   /* Newton workspace too small */
+
+/* Load a mechanism from the project's text format (see the design doc of the
+ * repository: elements, species with NASA-7 coefficients, reactions of the
+ * classes of Sec. 2.3: elementary, third-body, Lindemann/Troe/SRI falloff and
+ * chemically activated, PLOG, Chebyshev; reverse rates via K_c, explicit
+ * Arrhenius or irreversible).  Validates element balance and supported
+ * features, packs device tables on HIP device `hip_device` and returns an
+ * owned handle in *out.  Errors: PYJAC_E_IO, _PARSE, _UNSUPPORTED,
+ * _UNBALANCED, _NOMEM, _DEVICE; *out is left NULL on error. */
+pyjac_status pyjac_mech_load(const char* path, int32_t hip_device, pyjac_mech** out);
+
+/* Same as pyjac_mech_load, from a NUL-terminated text buffer. */
+pyjac_status pyjac_mech_load_string(const char* text, int32_t hip_device, pyjac_mech** out);
+
+/* Sizes and a 64-bit content hash of the parsed mechanism (any out may be NULL). */
+pyjac_status pyjac_mech_info(const pyjac_mech* mech, int32_t* n_species, int32_t* n_reactions,
+                             uint64_t* content_hash);
+
+/* Synchronizes the mechanism's device, then frees its tables and the handle.
+ * NULL is accepted and ignored. */
+pyjac_status pyjac_mech_free(pyjac_mech* mech);
+
+/* Reaction rates, production rates and the RHS (Sec. 2.1 Eqs. ode/dTdt,
+ * Sec. 2.3).  For each of n_states states reads phi[N][ld], p[ld] and writes
+ * whichever outputs are non-NULL:
+ *   rop_f    [N_R][ld]  forward rate of progress  R_f,i = k_f,i prod [X_j]^nu'_ji
+ *   rop_r    [N_R][ld]  reverse rate of progress  R_r,i = k_r,i prod [X_j]^nu''_ji
+ *   pres_mod [N_R][ld]  pressure modification c_i (Eq. rxn_pressure; 1 for
+ *                       elementary, PLOG and Chebyshev reactions)
+ *   wdot     [N][ld]    species production rates wdot_k = sum_i nu_ki c_i (R_f,i - R_r,i)
+ *   dphi     [N][ld]    f = dPhi/dt: dT/dt and dY_k/dt for k = 1..N-1
+ * Reaction index i is the order of the mechanism file.  n_states == 0 is a
+ * no-op.  Errors: PYJAC_E_INVALID (NULL mech/phi/p, n_states < 0, ld < n_states,
+ * misaligned pointer, wrong device), PYJAC_E_DEVICE. */
+pyjac_status pyjac_eval_rates(const pyjac_mech* mech, int64_t n_states, int64_t ld,
+                              const double* phi, const double* p, double* rop_f, double* rop_r,
+                              double* pres_mod, double* wdot, double* dphi, void* stream);
+
+/* Dense analytical Jacobian J = df/dPhi of the constant-pressure RHS
+ * (Sec. 3.1 elements, Sec. 3.2 evaluation order with the last-species
+ * placeholder row, Sec. 3.3: the matrix is dense).  Writes jac[N*N][ld]
+ * (row i = equation, column j = state variable; row/column 0 is temperature).
+ * Errors as pyjac_eval_rates; jac must be non-NULL. */
+pyjac_status pyjac_eval_jacobian(const pyjac_mech* mech, int64_t n_states, int64_t ld,
+                                 const double* phi, const double* p, double* jac, void* stream);
+
+/* Bytes of device workspace pyjac_newton_factor_solve needs for n_states
+ * states in `mode` (0 or 1).  Returns 0 for a bad handle or mode. */
+size_t pyjac_newton_workspace_bytes(const pyjac_mech* mech, int64_t n_states, int32_t mode);
+
+/* Batched solve of the Newton system of an implicit integrator step,
+ * A x = rhs with A = I - h_s * gamma * J_s for every state s (N x N, FP64
+ * Jacobian as written by pyjac_eval_jacobian, same layout and ld).
+ *   h      [ld]      per-state step size
+ *   rhs    [N][ld]   right-hand side b
+ *   x      [N][ld]   solution (may not alias rhs or jac)
+ *   mode 0: LU with partial pivoting in FP64.
+ *   mode 1: LU with partial pivoting in FP32 on the matrix cores, FP64
+ *           residual r = b - A x and up to max_refine refinement sweeps until
+ *           ||dx||_inf <= rtol * ||x||_inf; a state that does not converge is
+ *           re-solved in FP64 (counted in info).
+ *   info   [ld]      >= 0: refinement sweeps used (mode 1; 0 for mode 0);
+ *                    -1: zero pivot (singular A); -2: mode-1 state fell back to
+ *                    FP64 and converged there; -3: non-finite input.
+ * workspace must hold pyjac_newton_workspace_bytes(mech, n_states, mode)
+ * device bytes (it may be NULL when that is 0).  Errors: PYJAC_E_INVALID,
+ * PYJAC_E_WORKSPACE, PYJAC_E_DEVICE. */
+pyjac_status pyjac_newton_factor_solve(const pyjac_mech* mech, int64_t n_states, int64_t ld,
+                                       const double* jac, const double* h, double gamma,
+                                       const double* rhs, double* x, int32_t mode,
+                                       int32_t max_refine, double rtol, int32_t* info,
+                                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* Tuning: force the launch shape of one kernel family of this handle
+ * (which = 0: rates kernel, 1: Jacobian kernel) to tile_states states per
+ * workgroup and `threads` threads per workgroup; tile_states = 0 restores the
+ * automatic choice (largest tile whose LDS working set fits the device).
+ * Results per state do not depend on the shape (all per-state sums run in
+ * species order).  Not thread-safe against
+ * concurrent evaluation calls on the same handle.  Errors: PYJAC_E_INVALID,
+ * PYJAC_E_UNSUPPORTED (shape not compiled or does not fit). */
+pyjac_status pyjac_mech_set_variant(pyjac_mech* mech, int32_t which, int32_t tile_states,
+                                    int32_t threads);
+
+/* Current launch shape of a kernel family and its dynamic LDS bytes. */
+pyjac_status pyjac_mech_get_variant(const pyjac_mech* mech, int32_t which, int32_t* tile_states,
+                                    int32_t* threads, size_t* lds_bytes);
+
+/* Static description of a status code. */
+const char* pyjac_status_string(pyjac_status status);
+
+/* Thread-local detail for the last failing call on this thread ("" if none). */
+const char* pyjac_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PYJAC_MI355X_H */

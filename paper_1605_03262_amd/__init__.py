@@ -1,0 +1,130 @@
+"""MI355X (gfx950) library for the hot path of the analytical chemical-kinetics
+Jacobian of Niemeyer, Curtis & Sung (arXiv:1605.03262).
+
+The work happens in libpyjac_mi355x.so (HIP kernels behind the C ABI of
+include/pyjac.h).  `Mechanism` is a thin convenience wrapper: it takes torch
+tensors on the GPU, passes their device pointers and the current HIP stream,
+and allocates outputs.  PyTorch serves only as device memory and streams.
+"""
+from __future__ import annotations
+
+from . import _lib
+from ._lib import PyjacError, load_library  # noqa: F401
+
+NEWTON_FP64 = 0
+NEWTON_MIXED = 1
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Mechanism:
+    """A mechanism whose tables live on one GPU."""
+
+    def __init__(self, path: str | None = None, text: str | None = None, device: int = 0):
+        if (path is None) == (text is None):
+            raise ValueError("give exactly one of path or text")
+        self.device = device
+        self._h = (_lib.pyjac_mech_load(path, device) if path is not None
+                   else _lib.pyjac_mech_load_string(text, device))
+        self.n_species, self.n_reactions, self.content_hash = _lib.pyjac_mech_info(self._h)
+
+    @property
+    def handle(self) -> int:
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.pyjac_mech_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ helpers
+    def _check_in(self, phi, p):
+        torch = _torch()
+        N = self.n_species
+        if phi.dtype != torch.float64 or p.dtype != torch.float64:
+            raise TypeError("phi and p must be float64")
+        if not (phi.is_cuda and p.is_cuda):
+            raise TypeError("phi and p must be GPU tensors")
+        if phi.dim() != 2 or phi.shape[0] != N or phi.stride(1) != 1:
+            raise ValueError(f"phi must be [{N}, ld] with unit stride along states")
+        ld = phi.stride(0)
+        n = phi.shape[1]
+        if p.dim() != 1 or p.shape[0] < n or p.stride(0) != 1:
+            raise ValueError("p must be a contiguous vector of at least n_states entries")
+        return n, ld
+
+    @staticmethod
+    def _stream():
+        return _torch().cuda.current_stream().cuda_stream
+
+    @staticmethod
+    def _ptr(t):
+        return None if t is None else t.data_ptr()
+
+    # ----------------------------------------------------------- kernels
+    def eval_rates(self, phi, p, rop_f=True, rop_r=True, pres_mod=True, wdot=True, dphi=True):
+        """Rates, production rates and the RHS; returns a dict of [*, ld] tensors."""
+        torch = _torch()
+        n, ld = self._check_in(phi, p)
+        N, NR = self.n_species, self.n_reactions
+        out = {}
+        mk = lambda rows: torch.empty((rows, ld), dtype=torch.float64, device=phi.device)  # noqa: E731
+        for name, flag, rows in (("rop_f", rop_f, NR), ("rop_r", rop_r, NR),
+                                 ("pres_mod", pres_mod, NR), ("wdot", wdot, N), ("dphi", dphi, N)):
+            out[name] = mk(rows) if flag is True else (flag if flag is not False else None)
+        _lib.pyjac_eval_rates(self._h, n, ld, phi.data_ptr(), p.data_ptr(),
+                              self._ptr(out["rop_f"]), self._ptr(out["rop_r"]),
+                              self._ptr(out["pres_mod"]), self._ptr(out["wdot"]),
+                              self._ptr(out["dphi"]), self._stream())
+        return {k: v for k, v in out.items() if v is not None}
+
+    def eval_jacobian(self, phi, p, out=None):
+        """Dense Jacobian, a [N*N, ld] tensor (element i*N + j is dF_i/dPhi_j)."""
+        torch = _torch()
+        n, ld = self._check_in(phi, p)
+        N = self.n_species
+        if out is None:
+            out = torch.empty((N * N, ld), dtype=torch.float64, device=phi.device)
+        elif out.shape[0] != N * N or out.stride(0) != ld or out.stride(1) != 1:
+            raise ValueError("out must be [N*N, ld] with the same ld as phi")
+        _lib.pyjac_eval_jacobian(self._h, n, ld, phi.data_ptr(), p.data_ptr(), out.data_ptr(),
+                                 self._stream())
+        return out
+
+    def newton_workspace_bytes(self, n_states: int, mode: int) -> int:
+        return _lib.pyjac_newton_workspace_bytes(self._h, n_states, mode)
+
+    def newton_solve(self, jac, h, rhs, gamma: float, mode: int = NEWTON_MIXED,
+                     max_refine: int = 10, rtol: float = 1e-14, workspace=None):
+        """Solve (I - h gamma J) x = rhs per state; returns (x, info)."""
+        torch = _torch()
+        N = self.n_species
+        ld = rhs.stride(0)
+        n = rhs.shape[1]
+        if jac.stride(0) != ld or h.shape[0] < n:
+            raise ValueError("jac, rhs must share ld; h must cover n_states")
+        x = torch.empty((N, ld), dtype=torch.float64, device=rhs.device)
+        info = torch.empty((ld,), dtype=torch.int32, device=rhs.device)
+        need = self.newton_workspace_bytes(n, mode)
+        if workspace is None and need:
+            workspace = torch.empty((need,), dtype=torch.uint8, device=rhs.device)
+        wsb = 0 if workspace is None else workspace.numel() * workspace.element_size()
+        _lib.pyjac_newton_factor_solve(self._h, n, ld, jac.data_ptr(), h.data_ptr(), float(gamma),
+                                       rhs.data_ptr(), x.data_ptr(), mode, max_refine, rtol,
+                                       info.data_ptr(), self._ptr(workspace), wsb, self._stream())
+        return x, info
+
+    def set_variant(self, which: int, tile_states: int, threads: int) -> None:
+        _lib.pyjac_mech_set_variant(self._h, which, tile_states, threads)
+
+    def get_variant(self, which: int):
+        return _lib.pyjac_mech_get_variant(self._h, which)

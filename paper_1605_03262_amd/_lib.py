@@ -1,0 +1,139 @@
+"""ctypes binding of libpyjac_mi355x.so (C ABI in include/pyjac.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Function names mirror the C entry points.  The library must have
+been built (paper_1605_03262_amd/build.py); importing this module on a tree
+without it raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpyjac_mi355x.so")
+
+PYJAC_OK = 0
+STATUS_NAMES = {0: "PYJAC_OK", -1: "PYJAC_E_INVALID", -2: "PYJAC_E_PARSE",
+                -3: "PYJAC_E_UNSUPPORTED", -4: "PYJAC_E_DEVICE", -5: "PYJAC_E_NOMEM",
+                -6: "PYJAC_E_IO", -7: "PYJAC_E_UNBALANCED", -8: "PYJAC_E_WORKSPACE"}
+
+# Every symbol include/pyjac.h declares.
+EXPORTED = ("pyjac_mech_load", "pyjac_mech_load_string", "pyjac_mech_info", "pyjac_mech_free",
+            "pyjac_eval_rates", "pyjac_eval_jacobian", "pyjac_newton_workspace_bytes",
+            "pyjac_newton_factor_solve", "pyjac_mech_set_variant", "pyjac_mech_get_variant",
+            "pyjac_status_string", "pyjac_last_error")
+
+
+class PyjacError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {detail}")
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1605_03262_amd/build.py "
+                          "(there is no fallback implementation)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    st = ctypes.c_int32
+    lib.pyjac_mech_load.argtypes = [ctypes.c_char_p, i32, ctypes.POINTER(vp)]
+    lib.pyjac_mech_load.restype = st
+    lib.pyjac_mech_load_string.argtypes = [ctypes.c_char_p, i32, ctypes.POINTER(vp)]
+    lib.pyjac_mech_load_string.restype = st
+    lib.pyjac_mech_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                    ctypes.POINTER(ctypes.c_uint64)]
+    lib.pyjac_mech_info.restype = st
+    lib.pyjac_mech_free.argtypes = [vp]
+    lib.pyjac_mech_free.restype = st
+    lib.pyjac_eval_rates.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.pyjac_eval_rates.restype = st
+    lib.pyjac_eval_jacobian.argtypes = [vp, i64, i64, vp, vp, vp, vp]
+    lib.pyjac_eval_jacobian.restype = st
+    lib.pyjac_newton_workspace_bytes.argtypes = [vp, i64, i32]
+    lib.pyjac_newton_workspace_bytes.restype = sz
+    lib.pyjac_newton_factor_solve.argtypes = [vp, i64, i64, vp, vp, ctypes.c_double, vp, vp, i32,
+                                              i32, ctypes.c_double, vp, vp, sz, vp]
+    lib.pyjac_newton_factor_solve.restype = st
+    lib.pyjac_mech_set_variant.argtypes = [vp, i32, i32, i32]
+    lib.pyjac_mech_set_variant.restype = st
+    lib.pyjac_mech_get_variant.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                           ctypes.POINTER(sz)]
+    lib.pyjac_mech_get_variant.restype = st
+    lib.pyjac_status_string.argtypes = [st]
+    lib.pyjac_status_string.restype = ctypes.c_char_p
+    lib.pyjac_last_error.argtypes = []
+    lib.pyjac_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(status: int, where: str) -> None:
+    if status != PYJAC_OK:
+        detail = load_library().pyjac_last_error().decode()
+        raise PyjacError(status, where, detail)
+
+
+# ---------------------------------------------------------- thin C mirrors
+def pyjac_mech_load(path: str, device: int = 0) -> int:
+    h = ctypes.c_void_p()
+    check(load_library().pyjac_mech_load(path.encode(), device, ctypes.byref(h)), "pyjac_mech_load")
+    return h.value
+
+
+def pyjac_mech_load_string(text: str, device: int = 0) -> int:
+    h = ctypes.c_void_p()
+    check(load_library().pyjac_mech_load_string(text.encode(), device, ctypes.byref(h)),
+          "pyjac_mech_load_string")
+    return h.value
+
+
+def pyjac_mech_info(mech: int):
+    ns, nr, hh = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_uint64()
+    check(load_library().pyjac_mech_info(mech, ctypes.byref(ns), ctypes.byref(nr), ctypes.byref(hh)),
+          "pyjac_mech_info")
+    return ns.value, nr.value, hh.value
+
+
+def pyjac_mech_free(mech: int) -> None:
+    check(load_library().pyjac_mech_free(mech), "pyjac_mech_free")
+
+
+def pyjac_eval_rates(mech, n, ld, phi, p, rop_f, rop_r, pres_mod, wdot, dphi, stream) -> None:
+    check(load_library().pyjac_eval_rates(mech, n, ld, phi, p, rop_f, rop_r, pres_mod, wdot, dphi,
+                                          stream), "pyjac_eval_rates")
+
+
+def pyjac_eval_jacobian(mech, n, ld, phi, p, jac, stream) -> None:
+    check(load_library().pyjac_eval_jacobian(mech, n, ld, phi, p, jac, stream), "pyjac_eval_jacobian")
+
+
+def pyjac_newton_workspace_bytes(mech, n, mode) -> int:
+    return int(load_library().pyjac_newton_workspace_bytes(mech, n, mode))
+
+
+def pyjac_newton_factor_solve(mech, n, ld, jac, h, gamma, rhs, x, mode, max_refine, rtol, info,
+                              workspace, workspace_bytes, stream) -> None:
+    check(load_library().pyjac_newton_factor_solve(mech, n, ld, jac, h, gamma, rhs, x, mode,
+                                                   max_refine, rtol, info, workspace,
+                                                   workspace_bytes, stream),
+          "pyjac_newton_factor_solve")
+
+
+def pyjac_mech_set_variant(mech, which, tile_states, threads) -> None:
+    check(load_library().pyjac_mech_set_variant(mech, which, tile_states, threads),
+          "pyjac_mech_set_variant")
+
+
+def pyjac_mech_get_variant(mech, which):
+    ts, nt, lds = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+    check(load_library().pyjac_mech_get_variant(mech, which, ctypes.byref(ts), ctypes.byref(nt),
+                                                ctypes.byref(lds)), "pyjac_mech_get_variant")
+    return ts.value, nt.value, lds.value

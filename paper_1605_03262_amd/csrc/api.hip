@@ -1,0 +1,279 @@
+// C ABI of libpyjac_mi355x: mechanism handles, argument checking, variant
+// selection and kernel launches.  Declarations and contracts: include/pyjac.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/pyjac.h"
+#include "tables.hpp"
+
+namespace pyjac {
+
+size_t tile_lds_bytes(int N, int NR, int NG, int TS, int NT, bool jac);
+hipError_t launch_tile(bool jac_mode, int TS, int NT, const MechDev& md, int64_t n, int64_t ld,
+                       const double* phi, const double* p, double* rop_f, double* rop_r, double* pmod,
+                       double* wdot, double* dphi, double* jac, size_t lds, hipStream_t st);
+
+thread_local std::string g_last_error;
+
+pyjac_status fail(pyjac_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+struct Variant { int ts = 0, nt = 0; };
+
+}  // namespace pyjac
+
+struct pyjac_mech {
+  pyjac::PackedMech host;
+  pyjac::MechDev dev{};
+  void* dmem = nullptr;
+  int device = 0;
+  size_t max_lds = 65536;
+  pyjac::Variant jac_var, rates_var;
+};
+
+namespace pyjac {
+namespace {
+
+template <class T>
+void append(std::vector<char>& blob, const std::vector<T>& v, std::vector<size_t>& offs) {
+  size_t off = (blob.size() + 255) & ~size_t(255);
+  blob.resize(off + v.size() * sizeof(T));
+  std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+  offs.push_back(off);
+}
+
+int kpt_of(int N, int ts, int nt) { int g = nt / ts; return (N + g - 1) / g; }
+
+// Candidate launch shapes, most preferred first; the first that fits the
+// device's LDS and keeps <= 8 species per thread is used.
+Variant pick(const PackedMech& P, bool jac, size_t max_lds) {
+  static const int jac_c[][2] = {{16, 1024}, {8, 1024}, {8, 512}, {4, 1024}, {4, 512}, {2, 1024}, {2, 512}};
+  static const int rate_c[][2] = {{64, 1024}, {32, 1024}, {16, 1024}, {16, 512}, {8, 1024}, {8, 512},
+                                  {4, 1024}, {2, 1024}};
+  const auto* list = jac ? jac_c : rate_c;
+  int cnt = jac ? 7 : 8;
+  for (int c = 0; c < cnt; ++c) {
+    int ts = list[c][0], nt = list[c][1];
+    if (kpt_of(P.N, ts, nt) > 8) continue;
+    if (tile_lds_bytes(P.N, P.NR, P.NG, ts, nt, jac) <= max_lds) return {ts, nt};
+  }
+  return {0, 0};
+}
+
+pyjac_status upload(pyjac_mech* m) {
+  PackedMech& P = m->host;
+  std::vector<char> blob;
+  std::vector<size_t> o;
+  append(blob, P.W, o); append(blob, P.invW, o); append(blob, P.nasa, o); append(blob, P.tmid, o);
+  append(blob, P.vcol.empty() ? std::vector<double>{0.0} : P.vcol, o);
+  append(blob, P.rinfo, o); append(blob, P.rorig, o); append(blob, P.side, o); append(blob, P.net, o);
+  append(blob, P.coll_m, o); append(blob, P.gslot, o); append(blob, P.sum_f, o); append(blob, P.sum_r, o);
+  append(blob, P.arr, o); append(blob, P.fpar, o); append(blob, P.dnu_lnpr, o); append(blob, P.alphaN_m1, o);
+  append(blob, P.eff_ptr, o); append(blob, P.eff_sp, o); append(blob, P.eff_am1, o);
+  append(blob, P.plog_ptr, o); append(blob, P.plog, o); append(blob, P.cheb_off, o); append(blob, P.cheb, o);
+  append(blob, P.spg_ptr, o); append(blob, P.spg_rxn, o); append(blob, P.spg_nu, o);
+  append(blob, P.col_ptr, o); append(blob, P.term_src, o); append(blob, P.term_x, o); append(blob, P.term_coef, o);
+  if (hipMalloc(&m->dmem, blob.size()) != hipSuccess) return fail(PYJAC_E_NOMEM, "hipMalloc of mechanism tables failed");
+  if (hipMemcpy(m->dmem, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(PYJAC_E_DEVICE, "copy of mechanism tables failed");
+  char* b = static_cast<char*>(m->dmem);
+  size_t q = 0;
+  auto D = [&](auto ptr_type) { return reinterpret_cast<decltype(ptr_type)>(b + o[q++]); };
+  MechDev& d = m->dev;
+  d.N = P.N; d.NR = P.NR; d.NG = P.NG;
+  d.W = D((const double*)0); d.invW = D((const double*)0); d.nasa = D((const double*)0);
+  d.tmid = D((const double*)0); d.vcol = D((const double*)0);
+  d.rinfo = D((const int*)0); d.rorig = D((const int*)0); d.side = D((const int*)0); d.net = D((const int*)0);
+  d.coll_m = D((const int*)0); d.gslot = D((const int*)0); d.sum_f = D((const int*)0); d.sum_r = D((const int*)0);
+  d.arr = D((const double*)0); d.fpar = D((const double*)0); d.dnu_lnpr = D((const double*)0);
+  d.alphaN_m1 = D((const double*)0);
+  d.eff_ptr = D((const int*)0); d.eff_sp = D((const int*)0); d.eff_am1 = D((const double*)0);
+  d.plog_ptr = D((const int*)0); d.plog = D((const double*)0); d.cheb_off = D((const int*)0);
+  d.cheb = D((const double*)0);
+  d.spg_ptr = D((const int*)0); d.spg_rxn = D((const int*)0); d.spg_nu = D((const double*)0);
+  d.col_ptr = D((const int*)0); d.term_src = D((const int*)0); d.term_x = D((const int*)0);
+  d.term_coef = D((const double*)0);
+  return PYJAC_OK;
+}
+
+bool misaligned(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 7u); }
+
+pyjac_status check_common(const pyjac_mech* m, int64_t n, int64_t ld, const double* phi, const double* p) {
+  if (!m) return fail(PYJAC_E_INVALID, "mechanism handle is NULL");
+  if (n < 0) return fail(PYJAC_E_INVALID, "n_states is negative");
+  if (ld < n) return fail(PYJAC_E_INVALID, "ld is smaller than n_states");
+  if (n > 0 && (!phi || !p)) return fail(PYJAC_E_INVALID, "phi and p are required");
+  if (misaligned(phi) || misaligned(p)) return fail(PYJAC_E_INVALID, "input pointer not 8-byte aligned");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(PYJAC_E_DEVICE, "hipGetDevice failed");
+  if (cur != m->device) return fail(PYJAC_E_INVALID, "current HIP device differs from the mechanism's device");
+  if (ld > (int64_t)1 << 40) return fail(PYJAC_E_INVALID, "ld too large");
+  return PYJAC_OK;
+}
+
+}  // namespace
+}  // namespace pyjac
+
+using namespace pyjac;
+
+extern "C" {
+
+pyjac_status pyjac_mech_load_string(const char* text, int32_t hip_device, pyjac_mech** out) {
+  if (!out) return fail(PYJAC_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!text) return fail(PYJAC_E_INVALID, "text is NULL");
+  auto* m = new pyjac_mech();
+  std::string msg;
+  int rc = build_tables(text, m->host, msg);
+  if (rc != PYJAC_OK) { delete m; return fail(rc, msg); }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) {
+    delete m;
+    return fail(PYJAC_E_DEVICE, "no such HIP device");
+  }
+  m->device = hip_device;
+  int prev = 0;
+  hipGetDevice(&prev);
+  hipSetDevice(hip_device);
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) == hipSuccess && lds > 0)
+    m->max_lds = (size_t)lds;
+  rc = upload(m);
+  hipSetDevice(prev);
+  if (rc != PYJAC_OK) {
+    if (m->dmem) hipFree(m->dmem);
+    delete m;
+    return rc;
+  }
+  m->jac_var = pick(m->host, true, m->max_lds);
+  m->rates_var = pick(m->host, false, m->max_lds);
+  if (!m->jac_var.ts || !m->rates_var.ts) {
+    hipFree(m->dmem);
+    delete m;
+    return fail(PYJAC_E_UNSUPPORTED, "mechanism too large for the per-tile LDS budget");
+  }
+  *out = m;
+  return PYJAC_OK;
+}
+
+pyjac_status pyjac_mech_load(const char* path, int32_t hip_device, pyjac_mech** out) {
+  if (!out) return fail(PYJAC_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!path) return fail(PYJAC_E_INVALID, "path is NULL");
+  std::ifstream f(path, std::ios::binary);
+  if (!f) return fail(PYJAC_E_IO, std::string("cannot read ") + path);
+  std::stringstream ss;
+  ss << f.rdbuf();
+  return pyjac_mech_load_string(ss.str().c_str(), hip_device, out);
+}
+
+pyjac_status pyjac_mech_info(const pyjac_mech* m, int32_t* ns, int32_t* nr, uint64_t* hash) {
+  if (!m) return fail(PYJAC_E_INVALID, "mechanism handle is NULL");
+  if (ns) *ns = m->host.N;
+  if (nr) *nr = m->host.NR;
+  if (hash) *hash = m->host.hash;
+  return PYJAC_OK;
+}
+
+pyjac_status pyjac_mech_free(pyjac_mech* m) {
+  if (!m) return PYJAC_OK;
+  int prev = 0;
+  hipGetDevice(&prev);
+  hipSetDevice(m->device);
+  hipDeviceSynchronize();
+  if (m->dmem) hipFree(m->dmem);
+  hipSetDevice(prev);
+  delete m;
+  return PYJAC_OK;
+}
+
+pyjac_status pyjac_eval_rates(const pyjac_mech* m, int64_t n, int64_t ld, const double* phi, const double* p,
+                              double* rop_f, double* rop_r, double* pres_mod, double* wdot, double* dphi,
+                              void* stream) {
+  pyjac_status rc = check_common(m, n, ld, phi, p);
+  if (rc != PYJAC_OK) return rc;
+  for (const double* q : {rop_f, rop_r, pres_mod, wdot, dphi})
+    if (misaligned(q)) return fail(PYJAC_E_INVALID, "output pointer not 8-byte aligned");
+  if (n == 0) return PYJAC_OK;
+  const Variant v = m->rates_var;
+  size_t lds = tile_lds_bytes(m->host.N, m->host.NR, m->host.NG, v.ts, v.nt, false);
+  hipError_t e = launch_tile(false, v.ts, v.nt, m->dev, n, ld, phi, p, rop_f, rop_r, pres_mod, wdot, dphi,
+                             nullptr, lds, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("rates launch failed: ") + hipGetErrorString(e));
+  return PYJAC_OK;
+}
+
+pyjac_status pyjac_eval_jacobian(const pyjac_mech* m, int64_t n, int64_t ld, const double* phi, const double* p,
+                                 double* jac, void* stream) {
+  pyjac_status rc = check_common(m, n, ld, phi, p);
+  if (rc != PYJAC_OK) return rc;
+  if (n > 0 && !jac) return fail(PYJAC_E_INVALID, "jac is NULL");
+  if (misaligned(jac)) return fail(PYJAC_E_INVALID, "jac not 8-byte aligned");
+  if (n == 0) return PYJAC_OK;
+  const Variant v = m->jac_var;
+  size_t lds = tile_lds_bytes(m->host.N, m->host.NR, m->host.NG, v.ts, v.nt, true);
+  hipError_t e = launch_tile(true, v.ts, v.nt, m->dev, n, ld, phi, p, nullptr, nullptr, nullptr, nullptr,
+                             nullptr, jac, lds, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("jacobian launch failed: ") + hipGetErrorString(e));
+  return PYJAC_OK;
+}
+
+// Tuning hook: force the launch shape of one kernel family (which = 0 rates,
+// 1 Jacobian).  ts = 0 restores the automatic choice.  Returns
+// PYJAC_E_UNSUPPORTED when the shape does not fit the device or the mechanism.
+pyjac_status pyjac_mech_set_variant(pyjac_mech* m, int32_t which, int32_t ts, int32_t nt) {
+  if (!m || (which != 0 && which != 1)) return fail(PYJAC_E_INVALID, "bad handle or kernel id");
+  const bool jac = which == 1;
+  Variant v{ts, nt};
+  if (ts == 0) v = pick(m->host, jac, m->max_lds);
+  else {
+    if (ts <= 0 || nt <= 0 || nt % ts) return fail(PYJAC_E_INVALID, "bad variant");
+    if (kpt_of(m->host.N, ts, nt) > 8 || tile_lds_bytes(m->host.N, m->host.NR, m->host.NG, ts, nt, jac) > m->max_lds)
+      return fail(PYJAC_E_UNSUPPORTED, "variant does not fit");
+    static const int ok[][2] = {{16, 256}, {16, 512}, {16, 1024}, {8, 256}, {8, 512}, {8, 1024}, {4, 256},
+                                {4, 512},  {4, 1024}, {2, 512},   {2, 1024}, {32, 512}, {32, 1024}, {64, 1024}};
+    bool found = false;
+    for (auto& q : ok) found |= (q[0] == ts && q[1] == nt);
+    if (!found) return fail(PYJAC_E_UNSUPPORTED, "variant not compiled");
+  }
+  (jac ? m->jac_var : m->rates_var) = v;
+  return PYJAC_OK;
+}
+
+pyjac_status pyjac_mech_get_variant(const pyjac_mech* m, int32_t which, int32_t* ts, int32_t* nt,
+                                    size_t* lds_bytes) {
+  if (!m || (which != 0 && which != 1)) return fail(PYJAC_E_INVALID, "bad handle or kernel id");
+  const Variant v = which ? m->jac_var : m->rates_var;
+  if (ts) *ts = v.ts;
+  if (nt) *nt = v.nt;
+  if (lds_bytes) *lds_bytes = tile_lds_bytes(m->host.N, m->host.NR, m->host.NG, v.ts, v.nt, which == 1);
+  return PYJAC_OK;
+}
+
+const char* pyjac_status_string(pyjac_status s) {
+  switch (s) {
+    case PYJAC_OK: return "ok";
+    case PYJAC_E_INVALID: return "invalid argument";
+    case PYJAC_E_PARSE: return "mechanism parse error";
+    case PYJAC_E_UNSUPPORTED: return "unsupported feature";
+    case PYJAC_E_DEVICE: return "HIP device error";
+    case PYJAC_E_NOMEM: return "out of memory";
+    case PYJAC_E_IO: return "I/O error";
+    case PYJAC_E_UNBALANCED: return "reaction not element-balanced";
+    case PYJAC_E_WORKSPACE: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+const char* pyjac_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

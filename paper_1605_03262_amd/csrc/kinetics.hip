@@ -1,0 +1,567 @@
+// HIP kernels (gfx950) for reaction rates, production rates, the
+// constant-pressure RHS and its dense analytical Jacobian.
+//
+// Mapping: one workgroup owns a tile of TS consecutive states and NT threads;
+// thread t works on state s = t % TS of the tile and index group g = t / TS,
+// so every LDS array is laid out [index][TS] and every HBM access of a
+// per-state array touches TS consecutive doubles (element-major, state-fastest
+// layout).  All per-state temporaries of the tile stay in LDS:
+//   persistent : X[N+1] (concentrations, X[N] = 1), KF[NR] = c k_f,
+//                KR[NR] = c k_r, G[NG] = (dc/dE) R, per-state scalars
+//   alias      : phase A  Bk[N], dBk[N], per-species c_p terms [2][N]
+//                phase B  Bk[N], dBk[N], chunk[4][G] of per-reaction results
+//                phase C+ WA[N], WB[N], JT[N], H[N], per-species sum terms [2][N]
+// Every per-state sum over species is formed by one thread in species order
+// and no atomics are used, so a state's results depend neither on its
+// neighbours nor on the launch shape (TS, NT).
+//
+// Jacobian algebra (derived from the element formulas of Sec. 3.1, evaluated
+// in a reuse order of our own rather than Algorithm 2's dense per-reaction
+// update): for species rows k = 1..N (row N is the placeholder of Sec. 3.2)
+// and species columns j,
+//   J[k][j] = W_k (A_k v_j + B_k) / rho + sum_t coef_t P[src_t] X[x1_t] X[x2_t]
+// with v_j = 1/W_j - 1/W_N (from d rho/dY_j and d[X]/dY_j), A_k collecting
+// every term proportional to v_j, B_k the j-independent terms of the last
+// species, and the table terms the j-specific mass-action and third-body
+// efficiency derivatives.  The temperature row follows Sec. 3.2 (Eq. jac_dt)
+// and is accumulated while the species rows of a column are stored.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "tables.hpp"
+
+namespace pyjac {
+
+constexpr double kR = kGasConstant;
+constexpr double kLn10 = 2.302585092994045684;
+constexpr double kInvLn10 = 0.4342944819032518277;
+constexpr int NSC = 16;
+enum { SC_T = 0, SC_IT, SC_LT, SC_P, SC_LP, SC_L10P, SC_RHO, SC_W, SC_M, SC_CP, SC_DCP, SC_SHW, SC_J00 };
+
+// LDS layout in doubles; each entry counts rows of TS doubles.
+struct TileLayout {
+  int X, KF, KR, G, SC, alias;
+  int Bk, dBk, chunk, redA;      // phases A/B (alias)
+  int WA, WB, JT, H, redC;       // phases C/D (alias)
+  int rows;                      // total rows
+  __host__ __device__ TileLayout(int N, int NR, int NG, int Gr, bool jac) {
+    X = 0;
+    KF = X + N + 1;
+    KR = KF + (jac ? NR : 0);
+    G = KR + (jac ? NR : 0);
+    SC = G + (jac ? NG : 0);
+    alias = SC + NSC;
+    Bk = alias;
+    dBk = Bk + N;
+    redA = dBk + (jac ? N : 0);             // per-species terms summed in species order
+    chunk = redA;                           // phase B reuses the phase-A reduction rows
+    int endB = chunk + (jac ? 4 : 1) * Gr;
+    int endA = redA + (jac ? 2 : 1) * N;
+    WA = alias;
+    WB = WA + (jac ? N : 0);
+    JT = WB + (jac ? N : 0);
+    H = JT + (jac ? N : 0);
+    redC = H + (jac ? N : 0);
+    int endC = redC + (jac ? 2 : 1) * N;
+    int e = endB > endA ? endB : endA;
+    rows = e > endC ? e : endC;
+  }
+};
+
+struct RxnResult {
+  double q, thT, a, b, KF, KR, G, Rf, Rr, c;
+};
+
+__device__ inline double ipow_small(double x, int n) {
+  double r = 1.0;
+  for (int c = 0; c < n; ++c) r *= x;
+  return r;
+}
+
+// NASA-7 coefficient pointer for species k at temperature T.
+__device__ inline const double* nasa_coeffs(const MechDev& md, int k, double T) {
+  return md.nasa + (size_t)k * 14 + (T <= md.tmid[k] ? 0 : 7);
+}
+
+// Per-reaction evaluation for one state.  Xs points at X[0][s] (stride TS).
+template <int TS, bool JAC>
+__device__ inline void eval_reaction(const MechDev& md, int i, const double* Xs, const double* Bks,
+                                     const double* dBks, double T, double iT, double lT, double p,
+                                     double lp, double l10p, double rho, double W, double M,
+                                     RxnResult& o) {
+  const int info = md.rinfo[i];
+  const int kind = info & 0xF, blend = (info >> 4) & 0xF, rev = (info >> 8) & 0xF,
+            coll = (info >> 12) & 0xF;
+  const double* ar = md.arr + (size_t)i * kArrStride;
+  // ---- forward rate coefficient and D_f = T dln k_f/dT (Sec. 2.3, 2.3.4; Sec. 3.1)
+  double kf, Df;
+  if (kind <= K_CHEMACT) {
+    kf = ar[0] * exp(ar[1] * lT - ar[2] * iT);
+    Df = ar[1] + ar[2] * iT;
+  } else if (kind == K_PLOG) {
+    const int p0 = md.plog_ptr[i], p1 = md.plog_ptr[i + 1];
+    const double* pl = md.plog;
+    int lo = p0;
+    double frac = 0.0;
+    if (p1 - p0 > 1 && lp > pl[4 * p0]) {
+      if (lp >= pl[4 * (p1 - 1)]) lo = p1 - 1;
+      else {
+        for (int q = p0; q < p1 - 1; ++q) if (pl[4 * q] <= lp) lo = q;
+        frac = (lp - pl[4 * lo]) / (pl[4 * (lo + 1)] - pl[4 * lo]);
+      }
+    }
+    double lk1 = pl[4 * lo + 1] + pl[4 * lo + 2] * lT - pl[4 * lo + 3] * iT;
+    double D1 = pl[4 * lo + 2] + pl[4 * lo + 3] * iT;
+    if (frac != 0.0) {
+      int hi = lo + 1;
+      double lk2 = pl[4 * hi + 1] + pl[4 * hi + 2] * lT - pl[4 * hi + 3] * iT;
+      double D2 = pl[4 * hi + 2] + pl[4 * hi + 3] * iT;
+      lk1 = lk1 + (lk2 - lk1) * frac;
+      D1 = D1 + (D2 - D1) * frac;
+    }
+    kf = exp(lk1);
+    Df = D1;
+  } else {   // Chebyshev
+    const double* cb = md.cheb + md.cheb_off[i];
+    const int nT = (int)cb[0], nP = (int)cb[1];
+    const double xT = cb[2] * iT + cb[3];
+    const double xP = cb[4] * l10p + cb[5];
+    const double* eta = cb + 6;
+    double val = 0.0, dval = 0.0;
+    double Tm1 = 0.0, Tc = 1.0;        // T_{a-1}, T_a of the temperature variable
+    double Um2 = 0.0, Um1 = 0.0;       // U_{a-2}, U_{a-1}
+    for (int a = 0; a < nT; ++a) {
+      double e = 0.0, Pm1 = 0.0, Pc = 1.0;
+      for (int b = 0; b < nP; ++b) {
+        e += eta[a * nP + b] * Pc;
+        double Pn = (b == 0) ? xP : 2.0 * xP * Pc - Pm1;
+        Pm1 = Pc;
+        Pc = Pn;
+      }
+      val += e * Tc;
+      if (a > 0) dval += e * a * Um1;
+      double Tn = (a == 0) ? xT : 2.0 * xT * Tc - Tm1;
+      Tm1 = Tc;
+      Tc = Tn;
+      double Un = (a == 0) ? 1.0 : ((a == 1) ? 2.0 * xT : 2.0 * xT * Um1 - Um2);
+      Um2 = Um1;
+      Um1 = Un;
+    }
+    kf = exp(kLn10 * val);
+    Df = -kLn10 * dval * cb[2] * iT;
+  }
+  // ---- reverse rate coefficient (Sec. 2.3.1)
+  double kr = 0.0, Dr = 0.0;
+  const int* nt = md.net + (size_t)i * kNetStride;
+  if (rev == R_KC) {
+    double sB = 0.0, sdB = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxNet; ++q) {
+      int v = nt[q];
+      if (v == -1) break;
+      int k = v & 0xFFFF, nu = v >> 16;
+      sB += nu * Bks[k * TS];
+      if (JAC) sdB += nu * dBks[k * TS];
+    }
+    kr = kf * exp(-sB - md.dnu_lnpr[i]);
+    Dr = Df - T * sdB;
+  } else if (rev == R_EXPLICIT) {
+    kr = ar[6] * exp(ar[7] * lT - ar[8] * iT);
+    Dr = ar[7] + ar[8] * iT;
+  }
+  // ---- mass-action products
+  const int* sd = md.side + (size_t)i * kSideStride;
+  double pf = 1.0, pr = 1.0;
+#pragma unroll
+  for (int q = 0; q < kMaxSide; ++q) {
+    int v = sd[q];
+    if (v != -1) pf *= ipow_small(Xs[(v & 0xFFFF) * TS], v >> 16);
+    int w = sd[kMaxSide + q];
+    if (w != -1) pr *= ipow_small(Xs[(w & 0xFFFF) * TS], w >> 16);
+  }
+  const double Rf = kf * pf, Rr = kr * pr, Rn = Rf - Rr;
+  // ---- pressure modification (Sec. 2.3.2, 2.3.3) and its derivatives
+  double c = 1.0, psi = 0.0, dcdT = 0.0, E = 0.0;
+  if (coll != C_NONE) {
+    if (coll == C_SPECIES) E = Xs[md.coll_m[i] * TS];
+    else {
+      E = M;
+      for (int e = md.eff_ptr[i]; e < md.eff_ptr[i + 1]; ++e) E += md.eff_am1[e] * Xs[md.eff_sp[e] * TS];
+    }
+    if (kind == K_THD) {
+      c = E;
+      psi = 1.0;
+      dcdT = -E * iT;
+    } else {
+      const double ratio = ar[3] * exp(ar[4] * lT - ar[5] * iT);   // k0 / kinf
+      const double Pr = ratio * E;
+      double F = 1.0, Lam = 0.0, dlnFdT = 0.0;
+      const double* fp = md.fpar + (size_t)i * kFparStride;
+      if (blend == B_TROE) {
+        const double a = fp[0];
+        const double e3 = exp(-T / fp[1]), e1 = exp(-T / fp[2]);
+        double Fc = (1.0 - a) * e3 + a * e1;
+        double dFc = -(1.0 - a) / fp[1] * e3 - a / fp[2] * e1;
+        if (info & F_TROE_T2) {
+          double e2 = exp(-fp[3] * iT);
+          Fc += e2;
+          dFc += fp[3] * iT * iT * e2;
+        }
+        const double lnFc = log(Fc);
+        const double lFc = lnFc * kInvLn10, lPr = log(Pr) * kInvLn10;
+        const double At = lPr - 0.67 * lFc - 0.4;
+        const double Bt = 0.806 - 1.1762 * lFc - 0.14 * lPr;
+        const double r = At / Bt, den = 1.0 + r * r;
+        F = exp(lnFc / den);
+        const double den2B3 = den * den * Bt * Bt * Bt;
+        Lam = -lnFc * 2.0 * At * (Bt + 0.14 * At) * kInvLn10 / den2B3;
+        const double dAB = (-0.67 * Bt + 1.1762 * At) * kInvLn10 / Fc;   // (dA/dFc B - A dB/dFc)
+        const double dlnF_dFc = 1.0 / (Fc * den) - lnFc * 2.0 * At * dAB / den2B3;
+        dlnFdT = dlnF_dFc * dFc;
+      } else if (blend == B_SRI) {
+        const double ea = exp(-fp[1] * iT), ec = exp(-T / fp[2]);
+        const double base = fp[0] * ea + ec;
+        const double dbase = fp[0] * fp[1] * iT * iT * ea - ec / fp[2];
+        const double lPr = log(Pr) * kInvLn10;
+        const double Xs_ = 1.0 / (1.0 + lPr * lPr);
+        const double lnb = log(base);
+        F = fp[3] * exp(fp[4] * lT + Xs_ * lnb);
+        Lam = -lnb * Xs_ * Xs_ * 2.0 * lPr * kInvLn10;
+        dlnFdT = fp[4] * iT + Xs_ * dbase / base;
+      }
+      const double dlnPr = (ar[4] + ar[5] * iT - 1.0) * iT;   // (1/Pr) dPr/dT
+      double Phi;
+      if (kind == K_FALLOFF) {
+        c = Pr / (1.0 + Pr) * F;
+        Phi = 1.0 / (1.0 + Pr) + Lam;
+        psi = ratio * F * Phi / (1.0 + Pr);
+      } else {
+        c = F / (1.0 + Pr);
+        Phi = -Pr / (1.0 + Pr) + Lam;
+        psi = c * Phi / E;
+      }
+      dcdT = c * (Phi * dlnPr + dlnFdT);
+    }
+  }
+  o.Rf = Rf;
+  o.Rr = Rr;
+  o.c = c;
+  o.q = c * Rn;
+  if (JAC) {
+    const int sf = md.sum_f[i], sr = md.sum_r[i];
+    const double dRdT = (Rf * (Df - sf) - Rr * (Dr - sr)) * iT;
+    o.thT = (dcdT * Rn + c * (dRdT + Rn * iT)) / rho;
+    const double Gv = psi * Rn;
+    double kappa = 0.0, beta = 0.0;
+    if (coll == C_EFF) {
+      kappa = rho - E * W;
+      beta = -rho * md.alphaN_m1[i] * md.invW[md.N - 1];
+    } else if (coll == C_SPECIES) {
+      kappa = -E * W;
+      if (md.coll_m[i] == md.N - 1) beta = -rho * md.invW[md.N - 1];
+    }
+    o.a = -W * c * (Rf * sf - Rr * sr) + Gv * kappa;
+    double b = Gv * beta;
+    if (info & F_LAST_SPECIES) {
+      // c (k_f S'_N - k_r S''_N) with S'_N = d(prod [X]^nu')/d[X_N]
+      const int L = md.N - 1;
+      double SfN = 0.0, SrN = 0.0;
+      for (int side = 0; side < 2; ++side) {
+        double S = 0.0;
+        for (int q = 0; q < kMaxSide; ++q) {
+          int v = sd[side * kMaxSide + q];
+          if (v == -1 || (v & 0xFFFF) != L) continue;
+          int nuL = v >> 16;
+          double prod = nuL * ipow_small(Xs[L * TS], nuL - 1);
+          for (int u = 0; u < kMaxSide; ++u) {
+            int w = sd[side * kMaxSide + u];
+            if (w == -1 || u == q) continue;
+            prod *= ipow_small(Xs[(w & 0xFFFF) * TS], w >> 16);
+          }
+          S = prod;
+        }
+        if (side == 0) SfN = S; else SrN = S;
+      }
+      b += -c * rho * md.invW[L] * (kf * SfN - kr * SrN);
+    }
+    o.b = b;
+    o.KF = c * kf;
+    o.KR = c * kr;
+    o.G = Gv;
+  }
+}
+
+template <int TS, int NT, int KPT, bool JAC>
+__global__ __launch_bounds__(NT) void tile_kernel(MechDev md, int64_t n, int64_t ld,
+                                                  const double* __restrict__ phi,
+                                                  const double* __restrict__ pin,
+                                                  double* __restrict__ rop_f, double* __restrict__ rop_r,
+                                                  double* __restrict__ pmod, double* __restrict__ wdot_out,
+                                                  double* __restrict__ dphi_out, double* __restrict__ jac) {
+  constexpr int Gr = NT / TS;
+  extern __shared__ double lds[];
+  const int N = md.N, NR = md.NR, NG = md.NG;
+  const int tid = threadIdx.x, s = tid % TS, g = tid / TS;
+  const int64_t sg = (int64_t)blockIdx.x * TS + s;
+  const bool live = sg < n;
+  const int64_t sl = live ? sg : n - 1;
+  const TileLayout L(N, NR, NG, Gr, JAC);
+  double* X = lds + (size_t)L.X * TS + s;
+  double* SC = lds + (size_t)L.SC * TS + s;
+  double* Bk = lds + (size_t)L.Bk * TS + s;
+  double* dBk = lds + (size_t)L.dBk * TS + s;
+  double* red = lds + (size_t)L.redA * TS + s;
+
+  // ---- phase A1: mass fractions, Y_N, mean molecular weight, density (Sec. 2.1)
+  for (int k = g; k < N - 1; k += Gr) X[k * TS] = phi[(int64_t)(k + 1) * ld + sl];
+  __syncthreads();
+  if (g == 0) {
+    // Y_N = 1 - sum Y_k with Neumaier compensation: the difference can be
+    // tiny when the last species is scarce, so the sum is kept to ~1 ulp.
+    double sY = 0.0, cY = 0.0, sYW = 0.0;
+    for (int k = 0; k < N - 1; ++k) {
+      const double y = X[k * TS];
+      const double t = sY + y;
+      cY += (fabs(sY) >= fabs(y)) ? (sY - t) + y : (y - t) + sY;
+      sY = t;
+      sYW += y * md.invW[k];
+    }
+    const double YN = 1.0 - (sY + cY);
+    X[(N - 1) * TS] = YN;
+    X[N * TS] = 1.0;
+    sYW += YN * md.invW[N - 1];
+    const double T = phi[sl], p = pin[sl];
+    const double W = 1.0 / sYW;
+    SC[SC_T * TS] = T;
+    SC[SC_IT * TS] = 1.0 / T;
+    SC[SC_LT * TS] = log(T);
+    SC[SC_P * TS] = p;
+    const double lp = log(p);
+    SC[SC_LP * TS] = lp;
+    SC[SC_L10P * TS] = lp * kInvLn10;
+    SC[SC_W * TS] = W;
+    SC[SC_RHO * TS] = p * W / (kR * T);
+    SC[SC_M * TS] = p / (kR * T);
+  }
+  __syncthreads();
+  const double T = SC[SC_T * TS], iT = SC[SC_IT * TS], lT = SC[SC_LT * TS];
+  const double rho = SC[SC_RHO * TS], W = SC[SC_W * TS];
+
+  // ---- phase A2: concentrations and NASA-7 thermo (Sec. 2.2), B_k of Sec. 2.3.1
+  for (int k = g; k < N; k += Gr) {
+    const double y = X[k * TS];
+    X[k * TS] = rho * y * md.invW[k];
+    const double* a = nasa_coeffs(md, k, T);
+    const double cpR = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + a[4] * T)));
+    const double rW = kR * md.invW[k];
+    red[k * TS] = y * cpR * rW;
+    if (JAC) red[(N + k) * TS] = y * rW * (a[1] + T * (2.0 * a[2] + T * (3.0 * a[3] + 4.0 * a[4] * T)));
+    Bk[k * TS] = a[6] - a[0] + (a[0] - 1.0) * lT +
+                 T * (a[1] * 0.5 + T * (a[2] * (1.0 / 6.0) + T * (a[3] * (1.0 / 12.0) + a[4] * 0.05 * T))) -
+                 a[5] * iT;
+    if (JAC)
+      dBk[k * TS] = (a[0] - 1.0 + a[5] * iT) * iT + a[1] * 0.5 +
+                    T * (a[2] * (1.0 / 3.0) + T * (a[3] * 0.25 + a[4] * 0.2 * T));
+  }
+  __syncthreads();
+  if (g == 0) {
+    double c0 = 0.0, c1 = 0.0;
+    for (int k = 0; k < N; ++k) {
+      c0 += red[k * TS];
+      if (JAC) c1 += red[(N + k) * TS];
+    }
+    SC[SC_CP * TS] = c0;
+    SC[SC_DCP * TS] = c1;
+  }
+  __syncthreads();
+  const double p = SC[SC_P * TS], lp = SC[SC_LP * TS], l10p = SC[SC_L10P * TS];
+  const double M = SC[SC_M * TS];
+  const double cp = SC[SC_CP * TS];
+
+  // ---- phase B: reactions in chunks of Gr, gathered per species (no atomics)
+  double* chunk = lds + (size_t)L.chunk * TS + s;
+  double* KF = lds + (size_t)L.KF * TS + s;
+  double* KR = lds + (size_t)L.KR * TS + s;
+  double* Gs = lds + (size_t)L.G * TS + s;
+  double acc[KPT][4];
+  int cur[KPT], cend[KPT];
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int k = g + q * Gr;
+    acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.0;
+    cur[q] = (k < N) ? md.spg_ptr[k] : 0;
+    cend[q] = (k < N) ? md.spg_ptr[k + 1] : 0;
+  }
+  for (int c0 = 0; c0 < NR; c0 += Gr) {
+    const int i = c0 + g;
+    if (i < NR) {
+      RxnResult o;
+      eval_reaction<TS, JAC>(md, i, X, Bk, dBk, T, iT, lT, p, lp, l10p, rho, W, M, o);
+      chunk[g * TS] = o.q;
+      if (JAC) {
+        chunk[(Gr + g) * TS] = o.thT;
+        chunk[(2 * Gr + g) * TS] = o.a;
+        chunk[(3 * Gr + g) * TS] = o.b;
+        KF[i * TS] = o.KF;
+        KR[i * TS] = o.KR;
+        const int gs = md.gslot[i];
+        if (gs >= 0) Gs[gs * TS] = o.G;
+      } else if (live) {
+        const int64_t io = md.rorig[i];
+        if (rop_f) rop_f[io * ld + sg] = o.Rf;
+        if (rop_r) rop_r[io * ld + sg] = o.Rr;
+        if (pmod) pmod[io * ld + sg] = o.c;
+      }
+    }
+    __syncthreads();
+    const int cl = c0 + Gr;
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      while (cur[q] < cend[q] && md.spg_rxn[cur[q]] < cl) {
+        const int r = md.spg_rxn[cur[q]] - c0;
+        const double nu = md.spg_nu[cur[q]];
+        acc[q][0] += nu * chunk[r * TS];
+        if (JAC) {
+          acc[q][1] += nu * chunk[(Gr + r) * TS];
+          acc[q][2] += nu * chunk[(2 * Gr + r) * TS];
+          acc[q][3] += nu * chunk[(3 * Gr + r) * TS];
+        }
+        ++cur[q];
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- phase C: species terms, RHS (Eqs. ode, dTdt), J[0][0] sums
+  double* WA = lds + (size_t)L.WA * TS + s;
+  double* WB = lds + (size_t)L.WB * TS + s;
+  double* JT = lds + (size_t)L.JT * TS + s;
+  double* H = lds + (size_t)L.H * TS + s;
+  double* redc = lds + (size_t)L.redC * TS + s;
+  const double dcpdT = SC[SC_DCP * TS];
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int k = g + q * Gr;
+    if (k < N) {
+      const double wd = acc[q][0];
+      const double Wk = md.W[k];
+      const double* a = nasa_coeffs(md, k, T);
+      const double hRT = a[0] + T * (a[1] * 0.5 + T * (a[2] * (1.0 / 3.0) + T * (a[3] * 0.25 + a[4] * 0.2 * T))) +
+                         a[5] * iT;
+      const double hk = hRT * kR * T * md.invW[k];       // mass-specific enthalpy
+      redc[k * TS] = hk * Wk * wd;
+      if (JAC) {
+        const double cpk = (a[0] + T * (a[1] + T * (a[2] + T * (a[3] + a[4] * T)))) * kR * md.invW[k];
+        const double JTk = Wk * acc[q][1];
+        WA[k * TS] = Wk * (wd * W + acc[q][2]) / rho;
+        WB[k * TS] = Wk * acc[q][3] / rho;
+        JT[k * TS] = JTk;
+        H[k * TS] = hk;
+        redc[(N + k) * TS] = (cpk - hk / cp * dcpdT) * Wk * wd / rho + hk * JTk;
+      } else if (live) {
+        if (wdot_out) wdot_out[(int64_t)k * ld + sg] = wd;
+        if (dphi_out && k < N - 1) dphi_out[(int64_t)(k + 1) * ld + sg] = Wk * wd / rho;
+      }
+    }
+  }
+  __syncthreads();
+  if (g == 0) {
+    double a0 = 0.0, a1 = 0.0;
+    for (int k = 0; k < N; ++k) {
+      a0 += redc[k * TS];
+      if (JAC) a1 += redc[(N + k) * TS];
+    }
+    SC[SC_SHW * TS] = a0;
+    if (!JAC && live && dphi_out) dphi_out[sg] = -a0 / (rho * cp);
+    if (JAC && live) jac[sg] = -a1 / cp;
+  }
+  if (!JAC) return;
+  __syncthreads();
+
+  // ---- phase D: temperature column, species columns with the temperature row
+  const double Shw = SC[SC_SHW * TS];
+  const double* P = KF;     // KF, KR, G are contiguous
+  if (live)
+    for (int k = g; k < N - 1; k += Gr) jac[(int64_t)((k + 1) * N) * ld + sg] = JT[k * TS];
+  const double* aN = nasa_coeffs(md, N - 1, T);
+  const double cpN = (aN[0] + T * (aN[1] + T * (aN[2] + T * (aN[3] + aN[4] * T)))) * kR * md.invW[N - 1];
+  for (int j = g; j < N - 1; j += Gr) {
+    const double vj = md.vcol[j];
+    const int* cp_ = md.col_ptr + (size_t)j * N;
+    int t = cp_[0];
+    double TR = 0.0;
+    for (int k = 0; k < N; ++k) {
+      const int tend = cp_[k + 1];
+      double val = WA[k * TS] * vj + WB[k * TS];
+      for (; t < tend; ++t) {
+        const int src = md.term_src[t], x = md.term_x[t];
+        val += md.term_coef[t] * P[src * TS] * X[(x & 0xFFFF) * TS] * X[(x >> 16) * TS];
+      }
+      if (k < N - 1 && live) jac[(int64_t)((k + 1) * N + j + 1) * ld + sg] = val;
+      TR += H[k * TS] * val;
+    }
+    const double* aj = nasa_coeffs(md, j, T);
+    const double cpj = (aj[0] + T * (aj[1] + T * (aj[2] + T * (aj[3] + aj[4] * T)))) * kR * md.invW[j];
+    if (live) jac[(int64_t)(j + 1) * ld + sg] = -(-(cpj - cpN) / (rho * cp) * Shw + TR) / cp;
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+size_t tile_lds_bytes(int N, int NR, int NG, int TS, int NT, bool jac) {
+  TileLayout L(N, NR, NG, NT / TS, jac);
+  return (size_t)L.rows * TS * sizeof(double);
+}
+
+template <int TS, int NT, int KPT, bool JAC>
+static hipError_t launch_t(const MechDev& md, int64_t n, int64_t ld, const double* phi, const double* p,
+                           double* a, double* b, double* c, double* d, double* e, double* jac,
+                           size_t lds, hipStream_t st) {
+  auto kern = tile_kernel<TS, NT, KPT, JAC>;
+  hipError_t err = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  const int64_t tiles = (n + TS - 1) / TS;
+  hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(NT), lds, st, md, n, ld, phi, p, a, b, c, d, e, jac);
+  return hipGetLastError();
+}
+
+template <int TS, int NT, bool JAC>
+static hipError_t launch_k(int kpt, const MechDev& md, int64_t n, int64_t ld, const double* phi,
+                           const double* p, double* a, double* b, double* c, double* d, double* e,
+                           double* jac, size_t lds, hipStream_t st) {
+  if (kpt <= 1) return launch_t<TS, NT, 1, JAC>(md, n, ld, phi, p, a, b, c, d, e, jac, lds, st);
+  if (kpt <= 2) return launch_t<TS, NT, 2, JAC>(md, n, ld, phi, p, a, b, c, d, e, jac, lds, st);
+  if (kpt <= 4) return launch_t<TS, NT, 4, JAC>(md, n, ld, phi, p, a, b, c, d, e, jac, lds, st);
+  if (kpt <= 8) return launch_t<TS, NT, 8, JAC>(md, n, ld, phi, p, a, b, c, d, e, jac, lds, st);
+  return hipErrorInvalidValue;
+}
+
+// Supported (TS, NT) variants; species per thread kpt = ceil(N / (NT/TS)) <= 8.
+hipError_t launch_tile(bool jac_mode, int TS, int NT, const MechDev& md, int64_t n, int64_t ld,
+                       const double* phi, const double* p, double* rop_f, double* rop_r, double* pmod,
+                       double* wdot, double* dphi, double* jac, size_t lds, hipStream_t st) {
+  const int kpt = (md.N + NT / TS - 1) / (NT / TS);
+#define PYJAC_VARIANT(ts, nt)                                                                        \
+  if (TS == ts && NT == nt)                                                                          \
+    return jac_mode ? launch_k<ts, nt, true>(kpt, md, n, ld, phi, p, rop_f, rop_r, pmod, wdot, dphi, jac, lds, st) \
+                    : launch_k<ts, nt, false>(kpt, md, n, ld, phi, p, rop_f, rop_r, pmod, wdot, dphi, jac, lds, st);
+  PYJAC_VARIANT(16, 256)
+  PYJAC_VARIANT(16, 512)
+  PYJAC_VARIANT(16, 1024)
+  PYJAC_VARIANT(8, 256)
+  PYJAC_VARIANT(8, 512)
+  PYJAC_VARIANT(8, 1024)
+  PYJAC_VARIANT(4, 256)
+  PYJAC_VARIANT(4, 512)
+  PYJAC_VARIANT(4, 1024)
+  PYJAC_VARIANT(2, 512)
+  PYJAC_VARIANT(2, 1024)
+  PYJAC_VARIANT(32, 512)
+  PYJAC_VARIANT(32, 1024)
+  PYJAC_VARIANT(64, 1024)
+#undef PYJAC_VARIANT
+  return hipErrorInvalidValue;
+}
+
+}  // namespace pyjac

@@ -1,0 +1,257 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Gates (numbers fixed here, derived in the design doc):
+  * Jacobian: per-state relative Frobenius error E_norm <= 1e-10;
+  * R_f, R_r, c_i: elementwise relative error <= 1e-12;
+  * wdot, dPhi/dt: |error| <= 1e-12 of the gross (cancellation-free) magnitude.
+Inputs are the seeded synthetic mechanisms/states shared by both sides.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from conftest import ALL_KINDS, tiny
+from synth import ATM, config_mechanism, config_states, draw_states
+
+pytestmark = pytest.mark.gpu
+
+JAC_TOL = 1e-10
+RATE_TOL = 1e-12
+R = 8314.462618
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def Ref(oracle_built):
+    from oracle import RefMech
+    return RefMech
+
+
+def gpu_mech(mech):
+    from paper_1605_03262_amd import Mechanism
+    return Mechanism(text=mech.to_text())
+
+
+def dev(torch, a, ld=None):
+    a = np.asarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        ld = ld or a.shape[0]
+        out = np.full(ld, 101325.0)
+        out[: a.shape[0]] = a
+        return torch.from_numpy(out).cuda()
+    ld = ld or a.shape[1]
+    out = np.zeros((a.shape[0], ld))
+    out[:, : a.shape[1]] = a
+    out[0, a.shape[1]:] = 1500.0        # harmless padding states beyond n
+    out[1:, a.shape[1]:] = 1.0 / a.shape[0]
+    return torch.from_numpy(out).cuda()
+
+
+def gpu_rates(torch, M, phi, p, ld=None):
+    n = phi.shape[1]
+    dphi_, dp = dev(torch, phi, ld), dev(torch, p, ld)
+    view = dphi_.as_strided((phi.shape[0], n), (dphi_.stride(0), 1))
+    out = M.eval_rates(view, dp)
+    torch.cuda.synchronize()
+    return {k: v[:, :n].cpu().numpy() for k, v in out.items()}
+
+
+def gpu_jac(torch, M, phi, p, ld=None):
+    n = phi.shape[1]
+    dphi_, dp = dev(torch, phi, ld), dev(torch, p, ld)
+    view = dphi_.as_strided((phi.shape[0], n), (dphi_.stride(0), 1))
+    J = M.eval_jacobian(view, dp)
+    torch.cuda.synchronize()
+    return J[:, :n].cpu().numpy()
+
+
+def enorm_per_state(Jg, Jr):
+    """||Jg - Jr||_F / ||Jr||_F per state (column), scaled first so that huge
+    entries cannot overflow the sums of squares."""
+    scale = np.max(np.abs(Jr), axis=0)
+    scale[scale == 0] = 1.0
+    return np.linalg.norm((Jg - Jr) / scale, axis=0) / np.linalg.norm(Jr / scale, axis=0)
+
+
+def check_jac(Jg, Jr, label=""):
+    assert np.all(np.isfinite(Jg)), label
+    assert np.all(np.isfinite(Jr)), label
+    e = enorm_per_state(Jg, Jr)
+    assert e.max() <= JAC_TOL, f"{label}: max E_norm {e.max():.3e} at state {e.argmax()}"
+    return e
+
+
+def check_rates(og, orf, mech, phi, p, label=""):
+    for k in ("rop_f", "rop_r", "pres_mod"):
+        g, r = og[k], orf[k]
+        err = np.abs(g - r) <= RATE_TOL * np.abs(r) + 1e-300
+        assert err.all(), f"{label} {k}: worst rel {np.max(np.abs(g - r) / (np.abs(r) + 1e-300)):.3e}"
+    nf, nr = mech.stoich()
+    gross = np.abs(nr - nf) @ (np.abs(orf["pres_mod"]) * (orf["rop_f"] + orf["rop_r"]))
+    assert np.all(np.abs(og["wdot"] - orf["wdot"]) <= RATE_TOL * gross + 1e-300), label
+    W = mech.molecular_weights()
+    T = phi[0]
+    Y = np.vstack([phi[1:], 1 - phi[1:].sum(axis=0)])
+    Wmix = 1.0 / (Y / W[:, None]).sum(axis=0)
+    rho = p * Wmix / (R * T)
+    sp = (W[:-1, None] * gross[:-1] / rho)
+    assert np.all(np.abs(og["dphi"][1:] - orf["dphi"][1:]) <= RATE_TOL * sp + 1e-300), label
+    # temperature equation: scale by sum_k |h_k W_k| gross_k / (rho c_p) ~ |f_0| + gross
+    scale0 = np.abs(orf["dphi"][0]) + np.abs(og["dphi"][0]) + (W[:, None] * gross).sum(axis=0) * 1e4 / rho
+    assert np.all(np.abs(og["dphi"][0] - orf["dphi"][0]) <= 1e-11 * scale0), label
+
+
+# ------------------------------------------------------------ tiny mechanisms
+TINY_CASES = [(k, {k: 2, "elementary": 1}, "kc") for k in ALL_KINDS] + \
+             [(f"mixed{s}", None, None) for s in range(6)]
+
+
+@pytest.mark.parametrize("name,kinds,rev", TINY_CASES, ids=[c[0] for c in TINY_CASES])
+def test_tiny_parity(torch, Ref, name, kinds, rev):
+    if kinds is None:
+        s = int(name[5:])
+        rng = np.random.default_rng(900 + s)
+        kinds = {k: int(rng.integers(0, 2)) for k in ALL_KINDS}
+        kinds["elementary"] += 2
+        mech = tiny(700 + s, kinds, n_species=8, reactive_last=(s % 2 == 0),
+                    rev_mix={"kc": 2, "explicit": 1, "irrev": 1}, allow_shared=(s % 3 == 0))
+    else:
+        mech = tiny(500 + ALL_KINDS.index(name), kinds, rev_mix={rev: 1.0})
+    phi, p = draw_states(11, mech.n_species, 77, T=(700.0, 2400.0), P_atm=(0.3, 80.0),
+                         dirichlet=0.5)
+    ref = Ref(text=mech.to_text())
+    M = gpu_mech(mech)
+    check_rates(gpu_rates(torch, M, phi, p, ld=83), ref.eval_rates(phi, p), mech, phi, p, name)
+    check_jac(gpu_jac(torch, M, phi, p, ld=83), ref.eval_jacobian(phi, p), name)
+
+
+# --------------------------------------------------------- paper-shaped configs
+CONFIG_N = {0: 1000, 1: 1999, 2: 301, 3: 37}
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+def test_config_parity(torch, Ref, cfg):
+    mech = config_mechanism(cfg)
+    phi, p = config_states(cfg, CONFIG_N[cfg])
+    ref = Ref(text=mech.to_text())
+    M = gpu_mech(mech)
+    check_rates(gpu_rates(torch, M, phi, p), ref.eval_rates(phi, p), mech, phi, p, f"C{cfg}")
+    e = check_jac(gpu_jac(torch, M, phi, p), ref.eval_jacobian(phi, p), f"C{cfg}")
+    print(f"C{cfg}: n={phi.shape[1]} max E_norm {e.max():.2e} mean {e.mean():.2e}")
+
+
+@pytest.mark.parametrize("cfg,n_sample", [(1, 96), (2, 48), (3, 12)])
+def test_full_size_sampled(torch, Ref, cfg, n_sample):
+    """Full batch in the benchmark's launch configuration; sampled states are
+    recomputed one by one by the oracle."""
+    mech = config_mechanism(cfg)
+    phi, p = config_states(cfg)
+    n = phi.shape[1]
+    M = gpu_mech(mech)
+    dphi_, dp = torch.from_numpy(phi).cuda(), torch.from_numpy(p).cuda()
+    J = M.eval_jacobian(dphi_, dp)
+    rng = np.random.default_rng(cfg)
+    idx = np.unique(np.concatenate([[0, n - 1], rng.choice(n, n_sample, replace=False)]))
+    Js = J[:, torch.from_numpy(idx).cuda()].cpu().numpy()
+    del J
+    torch.cuda.empty_cache()
+    ref = Ref(text=mech.to_text())
+    Jr = ref.eval_jacobian(phi[:, idx], p[idx])
+    e = check_jac(Js, Jr, f"C{cfg} full")
+    print(f"C{cfg} full n={n}: sampled {len(idx)} max E_norm {e.max():.2e}")
+
+
+# ---------------------------------------------------------------- determinism
+def test_batch_independence_and_repeatability(torch):
+    mech = config_mechanism(1)
+    phi, p = config_states(1, 333)
+    M = gpu_mech(mech)
+    J1 = gpu_jac(torch, M, phi, p)
+    J2 = gpu_jac(torch, M, phi, p)
+    assert np.array_equal(J1, J2)
+    Jpad = gpu_jac(torch, M, phi, p, ld=341)
+    assert np.array_equal(J1, Jpad)
+    perm = np.random.default_rng(0).permutation(phi.shape[1])
+    Jp = gpu_jac(torch, M, phi[:, perm], p[perm])
+    assert np.array_equal(J1[:, perm], Jp)
+    for s in (0, 17, 332):
+        Js = gpu_jac(torch, M, phi[:, s:s + 1], p[s:s + 1])
+        assert np.array_equal(J1[:, s:s + 1], Js)
+    r1 = gpu_rates(torch, M, phi, p)
+    r2 = gpu_rates(torch, M, phi[:, perm], p[perm])
+    for k in r1:
+        assert np.array_equal(r1[k][:, perm], r2[k])
+
+
+def test_launch_shape_does_not_change_results(torch):
+    mech = config_mechanism(1)
+    phi, p = config_states(1, 200)
+    M = gpu_mech(mech)
+    base_j = gpu_jac(torch, M, phi, p)
+    base_r = gpu_rates(torch, M, phi, p)
+    tried = 0
+    for ts, nt in ((8, 512), (8, 1024), (4, 512), (16, 1024), (4, 1024)):
+        try:
+            M.set_variant(1, ts, nt)
+            M.set_variant(0, ts, nt)
+        except Exception:
+            continue
+        tried += 1
+        assert np.array_equal(base_j, gpu_jac(torch, M, phi, p)), (ts, nt)
+        r = gpu_rates(torch, M, phi, p)
+        for k in r:
+            assert np.array_equal(base_r[k], r[k]), (ts, nt, k)
+    assert tried >= 2
+
+
+# ---------------------------------------------------------------- edge cases
+def test_edge_cases(torch):
+    from paper_1605_03262_amd import PyjacError
+    mech = config_mechanism(0)
+    M = gpu_mech(mech)
+    N = mech.n_species
+    phi = torch.zeros((N, 4), dtype=torch.float64, device="cuda")
+    p = torch.zeros(4, dtype=torch.float64, device="cuda")
+    # n = 0 is a no-op
+    M.eval_jacobian(phi[:, :0], p)
+    M.eval_rates(phi[:, :0], p)
+    from paper_1605_03262_amd import _lib
+    with pytest.raises(PyjacError):
+        _lib.pyjac_eval_jacobian(M.handle, 4, 3, phi.data_ptr(), p.data_ptr(), phi.data_ptr(), None)
+    with pytest.raises(PyjacError):
+        _lib.pyjac_eval_jacobian(M.handle, -1, 4, phi.data_ptr(), p.data_ptr(), phi.data_ptr(), None)
+    with pytest.raises(PyjacError):
+        _lib.pyjac_eval_jacobian(M.handle, 4, 4, None, p.data_ptr(), phi.data_ptr(), None)
+    with pytest.raises(PyjacError):
+        _lib.pyjac_eval_jacobian(M.handle, 4, 4, phi.data_ptr() + 4, p.data_ptr(), phi.data_ptr(), None)
+
+
+def test_nasa_break_and_extremes(torch, Ref):
+    """States at and next to the NASA range break (T = 1000 K) and at the ends of
+    the synthetic temperature range take the same branch on both sides."""
+    mech = config_mechanism(1)
+    phi, p = config_states(1, 12)
+    phi[0] = [1000.0, np.nextafter(1000.0, 0), np.nextafter(1000.0, 2000), 999.999, 1000.001,
+              800.0, 2200.0, 300.0, 3000.0, 1000.0, 1500.0, 1000.0]
+    p[-3:] = [ATM, 50 * ATM, 0.5 * ATM]
+    ref = Ref(text=mech.to_text())
+    M = gpu_mech(mech)
+    check_jac(gpu_jac(torch, M, phi, p), ref.eval_jacobian(phi, p), "NASA break")
+    check_rates(gpu_rates(torch, M, phi, p), ref.eval_rates(phi, p), mech, phi, p, "NASA break")
+
+
+def test_native_library_is_in_tree(torch):
+    import paper_1605_03262_amd as pkg
+    from paper_1605_03262_amd import _lib
+    lib = _lib.load_library()
+    assert os.path.dirname(_lib.LIB_PATH) == os.path.dirname(pkg.__file__)
+    maps = open("/proc/self/maps").read()
+    assert _lib.LIB_PATH in maps
