@@ -38,6 +38,14 @@ struct pyjac_mech {
   int device = 0;
   size_t max_lds = 65536;
   pyjac::Variant jac_var, rates_var;
+  // per launch shape: species-list chunk bounds, built when the shape is chosen
+  struct VarDev {
+    int ts = 0, nt = 0;
+    bool jac = false;
+    void* mem = nullptr;
+    const int* chunk = nullptr;
+  };
+  std::vector<VarDev> vars;
 };
 
 namespace pyjac {
@@ -58,7 +66,7 @@ int kpt_of(int N, int ts, int nt) { int g = nt / ts; return (N + g - 1) / g; }
 Variant pick(const PackedMech& P, bool jac, size_t max_lds) {
   static const int jac_c[][2] = {{16, 1024}, {8, 1024}, {8, 512}, {4, 1024}, {4, 512}, {2, 1024}, {2, 512}};
   static const int rate_c[][2] = {{64, 1024}, {32, 1024}, {16, 1024}, {16, 512}, {8, 1024}, {8, 512},
-                                  {4, 1024}, {2, 1024}};
+                                  {4, 1024}, {2, 1024}};   // all compiled shapes
   const auto* list = jac ? jac_c : rate_c;
   int cnt = jac ? 7 : 8;
   for (int c = 0; c < cnt; ++c) {
@@ -75,13 +83,10 @@ pyjac_status upload(pyjac_mech* m) {
   std::vector<size_t> o;
   append(blob, P.W, o); append(blob, P.invW, o); append(blob, P.nasa, o); append(blob, P.tmid, o);
   append(blob, P.vcol.empty() ? std::vector<double>{0.0} : P.vcol, o);
-  append(blob, P.rinfo, o); append(blob, P.rorig, o); append(blob, P.side, o); append(blob, P.net, o);
-  append(blob, P.coll_m, o); append(blob, P.gslot, o); append(blob, P.sum_f, o); append(blob, P.sum_r, o);
-  append(blob, P.arr, o); append(blob, P.fpar, o); append(blob, P.dnu_lnpr, o); append(blob, P.alphaN_m1, o);
-  append(blob, P.eff_ptr, o); append(blob, P.eff_sp, o); append(blob, P.eff_am1, o);
-  append(blob, P.plog_ptr, o); append(blob, P.plog, o); append(blob, P.cheb_off, o); append(blob, P.cheb, o);
-  append(blob, P.spg_ptr, o); append(blob, P.spg_rxn, o); append(blob, P.spg_nu, o);
-  append(blob, P.col_ptr, o); append(blob, P.term_src, o); append(blob, P.term_x, o); append(blob, P.term_coef, o);
+  append(blob, P.rx, o);
+  append(blob, P.eff_sp, o); append(blob, P.eff_am1, o); append(blob, P.plog, o); append(blob, P.cheb, o);
+  append(blob, P.spg_ent, o);
+  append(blob, P.col_start, o); append(blob, P.colrec, o);
   if (hipMalloc(&m->dmem, blob.size()) != hipSuccess) return fail(PYJAC_E_NOMEM, "hipMalloc of mechanism tables failed");
   if (hipMemcpy(m->dmem, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess)
     return fail(PYJAC_E_DEVICE, "copy of mechanism tables failed");
@@ -92,17 +97,42 @@ pyjac_status upload(pyjac_mech* m) {
   d.N = P.N; d.NR = P.NR; d.NG = P.NG;
   d.W = D((const double*)0); d.invW = D((const double*)0); d.nasa = D((const double*)0);
   d.tmid = D((const double*)0); d.vcol = D((const double*)0);
-  d.rinfo = D((const int*)0); d.rorig = D((const int*)0); d.side = D((const int*)0); d.net = D((const int*)0);
-  d.coll_m = D((const int*)0); d.gslot = D((const int*)0); d.sum_f = D((const int*)0); d.sum_r = D((const int*)0);
-  d.arr = D((const double*)0); d.fpar = D((const double*)0); d.dnu_lnpr = D((const double*)0);
-  d.alphaN_m1 = D((const double*)0);
-  d.eff_ptr = D((const int*)0); d.eff_sp = D((const int*)0); d.eff_am1 = D((const double*)0);
-  d.plog_ptr = D((const int*)0); d.plog = D((const double*)0); d.cheb_off = D((const int*)0);
+  d.rx = D((const RxnRec*)0);
+  d.eff_sp = D((const int*)0); d.eff_am1 = D((const double*)0); d.plog = D((const double*)0);
   d.cheb = D((const double*)0);
-  d.spg_ptr = D((const int*)0); d.spg_rxn = D((const int*)0); d.spg_nu = D((const double*)0);
-  d.col_ptr = D((const int*)0); d.term_src = D((const int*)0); d.term_x = D((const int*)0);
-  d.term_coef = D((const double*)0);
+  d.spg_ent = D((const int*)0);
+  d.col_start = D((const int*)0); d.colrec = D((const ColRec*)0);
+  d.spg_chunk = nullptr;
   return PYJAC_OK;
+}
+
+// Device data of one launch shape (built once per shape and kernel family).
+pyjac_status ensure_var(pyjac_mech* m, Variant v, bool jac) {
+  for (auto& e : m->vars) if (e.ts == v.ts && e.nt == v.nt && e.jac == jac) return PYJAC_OK;
+  pyjac_mech::VarDev vd;
+  vd.ts = v.ts; vd.nt = v.nt; vd.jac = jac;
+  std::vector<char> blob;
+  std::vector<size_t> o;
+  append(blob, species_chunk_bounds(m->host, v.nt / v.ts), o);
+  int prev = 0;
+  hipGetDevice(&prev);
+  hipSetDevice(m->device);
+  hipError_t e1 = hipMalloc(&vd.mem, blob.size());
+  hipError_t e2 = e1 == hipSuccess ? hipMemcpy(vd.mem, blob.data(), blob.size(), hipMemcpyHostToDevice) : e1;
+  hipSetDevice(prev);
+  if (e1 != hipSuccess) return fail(PYJAC_E_NOMEM, "hipMalloc of launch tables failed");
+  if (e2 != hipSuccess) { hipFree(vd.mem); return fail(PYJAC_E_DEVICE, "copy of launch tables failed"); }
+  char* b = static_cast<char*>(vd.mem);
+  vd.chunk = reinterpret_cast<const int*>(b + o[0]);
+  m->vars.push_back(vd);
+  return PYJAC_OK;
+}
+
+MechDev launch_view(const pyjac_mech* m, Variant v, bool jac) {
+  MechDev md = m->dev;
+  for (auto& e : m->vars)
+    if (e.ts == v.ts && e.nt == v.nt && e.jac == jac) md.spg_chunk = e.chunk;
+  return md;
 }
 
 bool misaligned(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 7u); }
@@ -161,6 +191,12 @@ pyjac_status pyjac_mech_load_string(const char* text, int32_t hip_device, pyjac_
     delete m;
     return fail(PYJAC_E_UNSUPPORTED, "mechanism too large for the per-tile LDS budget");
   }
+  rc = ensure_var(m, m->jac_var, true);
+  if (rc == PYJAC_OK) rc = ensure_var(m, m->rates_var, false);
+  if (rc != PYJAC_OK) {
+    pyjac_mech_free(m);
+    return rc;
+  }
   *out = m;
   return PYJAC_OK;
 }
@@ -191,6 +227,7 @@ pyjac_status pyjac_mech_free(pyjac_mech* m) {
   hipSetDevice(m->device);
   hipDeviceSynchronize();
   if (m->dmem) hipFree(m->dmem);
+  for (auto& e : m->vars) hipFree(e.mem);
   hipSetDevice(prev);
   delete m;
   return PYJAC_OK;
@@ -206,7 +243,8 @@ pyjac_status pyjac_eval_rates(const pyjac_mech* m, int64_t n, int64_t ld, const 
   if (n == 0) return PYJAC_OK;
   const Variant v = m->rates_var;
   size_t lds = tile_lds_bytes(m->host.N, m->host.NR, m->host.NG, v.ts, v.nt, false);
-  hipError_t e = launch_tile(false, v.ts, v.nt, m->dev, n, ld, phi, p, rop_f, rop_r, pres_mod, wdot, dphi,
+  const MechDev md = launch_view(m, v, false);
+  hipError_t e = launch_tile(false, v.ts, v.nt, md, n, ld, phi, p, rop_f, rop_r, pres_mod, wdot, dphi,
                              nullptr, lds, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("rates launch failed: ") + hipGetErrorString(e));
   return PYJAC_OK;
@@ -221,7 +259,8 @@ pyjac_status pyjac_eval_jacobian(const pyjac_mech* m, int64_t n, int64_t ld, con
   if (n == 0) return PYJAC_OK;
   const Variant v = m->jac_var;
   size_t lds = tile_lds_bytes(m->host.N, m->host.NR, m->host.NG, v.ts, v.nt, true);
-  hipError_t e = launch_tile(true, v.ts, v.nt, m->dev, n, ld, phi, p, nullptr, nullptr, nullptr, nullptr,
+  const MechDev md = launch_view(m, v, true);
+  hipError_t e = launch_tile(true, v.ts, v.nt, md, n, ld, phi, p, nullptr, nullptr, nullptr, nullptr,
                              nullptr, jac, lds, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("jacobian launch failed: ") + hipGetErrorString(e));
   return PYJAC_OK;
@@ -239,12 +278,14 @@ pyjac_status pyjac_mech_set_variant(pyjac_mech* m, int32_t which, int32_t ts, in
     if (ts <= 0 || nt <= 0 || nt % ts) return fail(PYJAC_E_INVALID, "bad variant");
     if (kpt_of(m->host.N, ts, nt) > 8 || tile_lds_bytes(m->host.N, m->host.NR, m->host.NG, ts, nt, jac) > m->max_lds)
       return fail(PYJAC_E_UNSUPPORTED, "variant does not fit");
-    static const int ok[][2] = {{16, 256}, {16, 512}, {16, 1024}, {8, 256}, {8, 512}, {8, 1024}, {4, 256},
-                                {4, 512},  {4, 1024}, {2, 512},   {2, 1024}, {32, 512}, {32, 1024}, {64, 1024}};
+    static const int ok[][2] = {{16, 512}, {16, 1024}, {8, 512}, {8, 1024}, {4, 512},
+                                {4, 1024}, {2, 512},  {2, 1024}, {32, 1024}, {64, 1024}};
     bool found = false;
     for (auto& q : ok) found |= (q[0] == ts && q[1] == nt);
     if (!found) return fail(PYJAC_E_UNSUPPORTED, "variant not compiled");
   }
+  pyjac_status rc = ensure_var(m, v, jac);
+  if (rc != PYJAC_OK) return rc;
   (jac ? m->jac_var : m->rates_var) = v;
   return PYJAC_OK;
 }
@@ -258,6 +299,15 @@ pyjac_status pyjac_mech_get_variant(const pyjac_mech* m, int32_t which, int32_t*
   if (lds_bytes) *lds_bytes = tile_lds_bytes(m->host.N, m->host.NR, m->host.NG, v.ts, v.nt, which == 1);
   return PYJAC_OK;
 }
+
+}  // extern "C"
+
+namespace pyjac {
+int mech_device(const pyjac_mech* m) { return m->device; }
+int mech_species(const pyjac_mech* m) { return m->host.N; }
+}  // namespace pyjac
+
+extern "C" {
 
 const char* pyjac_status_string(pyjac_status s) {
   switch (s) {

@@ -48,7 +48,7 @@ struct TileLayout {
   int rows;                      // total rows
   __host__ __device__ TileLayout(int N, int NR, int NG, int Gr, bool jac) {
     X = 0;
-    KF = X + N + 1;
+    KF = X + N + 1;                         // must directly follow X (padding reads X[N] as P[-1])
     KR = KF + (jac ? NR : 0);
     G = KR + (jac ? NR : 0);
     SC = G + (jac ? NG : 0);
@@ -59,9 +59,9 @@ struct TileLayout {
     chunk = redA;                           // phase B reuses the phase-A reduction rows
     int endB = chunk + (jac ? 4 : 1) * Gr;
     int endA = redA + (jac ? 2 : 1) * N;
-    WA = alias;
-    WB = WA + (jac ? N : 0);
-    JT = WB + (jac ? N : 0);
+    WA = alias;                             // WA and WB interleaved: [k][s][2]
+    WB = WA;
+    JT = WA + (jac ? 2 * N : 0);
     H = JT + (jac ? N : 0);
     redC = H + (jac ? N : 0);
     int endC = redC + (jac ? 2 : 1) * N;
@@ -85,23 +85,26 @@ __device__ inline const double* nasa_coeffs(const MechDev& md, int k, double T) 
   return md.nasa + (size_t)k * 14 + (T <= md.tmid[k] ? 0 : 7);
 }
 
-// Per-reaction evaluation for one state.  Xs points at X[0][s] (stride TS).
+// Per-reaction evaluation for one state.  Xs points at X[0][s] (stride TS);
+// R is the reaction's packed record, fetched by the caller before any branch.
 template <int TS, bool JAC>
-__device__ inline void eval_reaction(const MechDev& md, int i, const double* Xs, const double* Bks,
-                                     const double* dBks, double T, double iT, double lT, double p,
-                                     double lp, double l10p, double rho, double W, double M,
-                                     RxnResult& o) {
-  const int info = md.rinfo[i];
+__device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const RxnRec* __restrict__ Rg,
+                                     const double* Xs,
+                                     const double* Bks, const double* dBks, double T, double iT,
+                                     double lT, double lp, double l10p, double rho, double W,
+                                     double M, RxnResult& o) {
+  const int info = R.info;
   const int kind = info & 0xF, blend = (info >> 4) & 0xF, rev = (info >> 8) & 0xF,
             coll = (info >> 12) & 0xF;
-  const double* ar = md.arr + (size_t)i * kArrStride;
+  const double* ar = R.arr;          // primary Arrhenius (hot part of the record)
+  const double* arg = Rg->arr;       // secondary / reverse parameters, read where needed
   // ---- forward rate coefficient and D_f = T dln k_f/dT (Sec. 2.3, 2.3.4; Sec. 3.1)
   double kf, Df;
   if (kind <= K_CHEMACT) {
     kf = ar[0] * exp(ar[1] * lT - ar[2] * iT);
     Df = ar[1] + ar[2] * iT;
   } else if (kind == K_PLOG) {
-    const int p0 = md.plog_ptr[i], p1 = md.plog_ptr[i + 1];
+    const int p0 = R.aux0, p1 = R.aux1;
     const double* pl = md.plog;
     int lo = p0;
     double frac = 0.0;
@@ -124,7 +127,7 @@ __device__ inline void eval_reaction(const MechDev& md, int i, const double* Xs,
     kf = exp(lk1);
     Df = D1;
   } else {   // Chebyshev
-    const double* cb = md.cheb + md.cheb_off[i];
+    const double* cb = md.cheb + R.aux0;
     const int nT = (int)cb[0], nP = (int)cb[1];
     const double xT = cb[2] * iT + cb[3];
     const double xP = cb[4] * l10p + cb[5];
@@ -154,25 +157,24 @@ __device__ inline void eval_reaction(const MechDev& md, int i, const double* Xs,
   }
   // ---- reverse rate coefficient (Sec. 2.3.1)
   double kr = 0.0, Dr = 0.0;
-  const int* nt = md.net + (size_t)i * kNetStride;
   if (rev == R_KC) {
     double sB = 0.0, sdB = 0.0;
 #pragma unroll
     for (int q = 0; q < kMaxNet; ++q) {
-      int v = nt[q];
+      int v = R.net[q];
       if (v == -1) break;
       int k = v & 0xFFFF, nu = v >> 16;
       sB += nu * Bks[k * TS];
       if (JAC) sdB += nu * dBks[k * TS];
     }
-    kr = kf * exp(-sB - md.dnu_lnpr[i]);
+    kr = kf * exp(-sB - R.dnu_lnpr);
     Dr = Df - T * sdB;
   } else if (rev == R_EXPLICIT) {
-    kr = ar[6] * exp(ar[7] * lT - ar[8] * iT);
-    Dr = ar[7] + ar[8] * iT;
+    kr = arg[6] * exp(arg[7] * lT - arg[8] * iT);
+    Dr = arg[7] + arg[8] * iT;
   }
   // ---- mass-action products
-  const int* sd = md.side + (size_t)i * kSideStride;
+  const int* sd = R.side;
   double pf = 1.0, pr = 1.0;
 #pragma unroll
   for (int q = 0; q < kMaxSide; ++q) {
@@ -185,20 +187,21 @@ __device__ inline void eval_reaction(const MechDev& md, int i, const double* Xs,
   // ---- pressure modification (Sec. 2.3.2, 2.3.3) and its derivatives
   double c = 1.0, psi = 0.0, dcdT = 0.0, E = 0.0;
   if (coll != C_NONE) {
-    if (coll == C_SPECIES) E = Xs[md.coll_m[i] * TS];
+    if (coll == C_SPECIES) E = Xs[R.coll_m * TS];
     else {
       E = M;
-      for (int e = md.eff_ptr[i]; e < md.eff_ptr[i + 1]; ++e) E += md.eff_am1[e] * Xs[md.eff_sp[e] * TS];
+      if (coll == C_EFF)
+        for (int e = R.aux0; e < R.aux1; ++e) E += md.eff_am1[e] * Xs[md.eff_sp[e] * TS];
     }
     if (kind == K_THD) {
       c = E;
       psi = 1.0;
       dcdT = -E * iT;
     } else {
-      const double ratio = ar[3] * exp(ar[4] * lT - ar[5] * iT);   // k0 / kinf
+      const double ratio = arg[3] * exp(arg[4] * lT - arg[5] * iT);   // k0 / kinf
       const double Pr = ratio * E;
       double F = 1.0, Lam = 0.0, dlnFdT = 0.0;
-      const double* fp = md.fpar + (size_t)i * kFparStride;
+      const double* fp = Rg->fpar;
       if (blend == B_TROE) {
         const double a = fp[0];
         const double e3 = exp(-T / fp[1]), e1 = exp(-T / fp[2]);
@@ -231,7 +234,7 @@ __device__ inline void eval_reaction(const MechDev& md, int i, const double* Xs,
         Lam = -lnb * Xs_ * Xs_ * 2.0 * lPr * kInvLn10;
         dlnFdT = fp[4] * iT + Xs_ * dbase / base;
       }
-      const double dlnPr = (ar[4] + ar[5] * iT - 1.0) * iT;   // (1/Pr) dPr/dT
+      const double dlnPr = (arg[4] + arg[5] * iT - 1.0) * iT;   // (1/Pr) dPr/dT
       double Phi;
       if (kind == K_FALLOFF) {
         c = Pr / (1.0 + Pr) * F;
@@ -250,17 +253,17 @@ __device__ inline void eval_reaction(const MechDev& md, int i, const double* Xs,
   o.c = c;
   o.q = c * Rn;
   if (JAC) {
-    const int sf = md.sum_f[i], sr = md.sum_r[i];
+    const int sf = R.sum_f, sr = R.sum_r;
     const double dRdT = (Rf * (Df - sf) - Rr * (Dr - sr)) * iT;
     o.thT = (dcdT * Rn + c * (dRdT + Rn * iT)) / rho;
     const double Gv = psi * Rn;
     double kappa = 0.0, beta = 0.0;
     if (coll == C_EFF) {
       kappa = rho - E * W;
-      beta = -rho * md.alphaN_m1[i] * md.invW[md.N - 1];
+      beta = -rho * R.alphaN_m1 * md.invW[md.N - 1];
     } else if (coll == C_SPECIES) {
       kappa = -E * W;
-      if (md.coll_m[i] == md.N - 1) beta = -rho * md.invW[md.N - 1];
+      if (R.coll_m == md.N - 1) beta = -rho * md.invW[md.N - 1];
     }
     o.a = -W * c * (Rf * sf - Rr * sr) + Gv * kappa;
     double b = Gv * beta;
@@ -294,7 +297,7 @@ __device__ inline void eval_reaction(const MechDev& md, int i, const double* Xs,
 }
 
 template <int TS, int NT, int KPT, bool JAC>
-__global__ __launch_bounds__(NT) void tile_kernel(MechDev md, int64_t n, int64_t ld,
+__global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev md, int64_t n, int64_t ld,
                                                   const double* __restrict__ phi,
                                                   const double* __restrict__ pin,
                                                   double* __restrict__ rop_f, double* __restrict__ rop_r,
@@ -386,19 +389,20 @@ __global__ __launch_bounds__(NT) void tile_kernel(MechDev md, int64_t n, int64_t
   double* KR = lds + (size_t)L.KR * TS + s;
   double* Gs = lds + (size_t)L.G * TS + s;
   double acc[KPT][4];
-  int cur[KPT], cend[KPT];
 #pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int k = g + q * Gr;
-    acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.0;
-    cur[q] = (k < N) ? md.spg_ptr[k] : 0;
-    cend[q] = (k < N) ? md.spg_ptr[k + 1] : 0;
-  }
-  for (int c0 = 0; c0 < NR; c0 += Gr) {
+  for (int q = 0; q < KPT; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.0;
+  for (int c0 = 0, ch = 0; c0 < NR; c0 += Gr, ++ch) {
     const int i = c0 + g;
     if (i < NR) {
+      RxnRec Rr;
+      {   // hot half of the record: 8 independent 16-byte loads
+        const int4* src = reinterpret_cast<const int4*>(md.rx + i);
+        int4* dst = reinterpret_cast<int4*>(&Rr);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) dst[u] = src[u];
+      }
       RxnResult o;
-      eval_reaction<TS, JAC>(md, i, X, Bk, dBk, T, iT, lT, p, lp, l10p, rho, W, M, o);
+      eval_reaction<TS, JAC>(md, Rr, md.rx + i, X, Bk, dBk, T, iT, lT, lp, l10p, rho, W, M, o);
       chunk[g * TS] = o.q;
       if (JAC) {
         chunk[(Gr + g) * TS] = o.thT;
@@ -406,37 +410,48 @@ __global__ __launch_bounds__(NT) void tile_kernel(MechDev md, int64_t n, int64_t
         chunk[(3 * Gr + g) * TS] = o.b;
         KF[i * TS] = o.KF;
         KR[i * TS] = o.KR;
-        const int gs = md.gslot[i];
-        if (gs >= 0) Gs[gs * TS] = o.G;
+        if (Rr.gslot >= 0) Gs[Rr.gslot * TS] = o.G;
       } else if (live) {
-        const int64_t io = md.rorig[i];
+        const int64_t io = Rr.orig;
         if (rop_f) rop_f[io * ld + sg] = o.Rf;
         if (rop_r) rop_r[io * ld + sg] = o.Rr;
         if (pmod) pmod[io * ld + sg] = o.c;
       }
     }
     __syncthreads();
-    const int cl = c0 + Gr;
+    // species gathers over this chunk: list entries [bnd[ch][k], bnd[ch+1][k]),
+    // fetched four at a time so their loads overlap
+    const int* bnd = md.spg_chunk + (size_t)ch * N;
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
-      while (cur[q] < cend[q] && md.spg_rxn[cur[q]] < cl) {
-        const int r = md.spg_rxn[cur[q]] - c0;
-        const double nu = md.spg_nu[cur[q]];
-        acc[q][0] += nu * chunk[r * TS];
-        if (JAC) {
-          acc[q][1] += nu * chunk[(Gr + r) * TS];
-          acc[q][2] += nu * chunk[(2 * Gr + r) * TS];
-          acc[q][3] += nu * chunk[(3 * Gr + r) * TS];
+      const int k = g + q * Gr;
+      if (k < N) {
+        const int e1 = bnd[N + k];
+        for (int e = bnd[k]; e < e1; e += 4) {
+          int ent[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) ent[u] = md.spg_ent[e + u];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (e + u < e1) {
+              const int r = (ent[u] & 0xFFFF) - c0;
+              const double nu = (double)(ent[u] >> 16);
+              acc[q][0] += nu * chunk[r * TS];
+              if (JAC) {
+                acc[q][1] += nu * chunk[(Gr + r) * TS];
+                acc[q][2] += nu * chunk[(2 * Gr + r) * TS];
+                acc[q][3] += nu * chunk[(3 * Gr + r) * TS];
+              }
+            }
+          }
         }
-        ++cur[q];
       }
     }
     __syncthreads();
   }
 
   // ---- phase C: species terms, RHS (Eqs. ode, dTdt), J[0][0] sums
-  double* WA = lds + (size_t)L.WA * TS + s;
-  double* WB = lds + (size_t)L.WB * TS + s;
+  double2* WAB = reinterpret_cast<double2*>(lds + (size_t)L.WA * TS) + s;
   double* JT = lds + (size_t)L.JT * TS + s;
   double* H = lds + (size_t)L.H * TS + s;
   double* redc = lds + (size_t)L.redC * TS + s;
@@ -455,8 +470,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(MechDev md, int64_t n, int64_t
       if (JAC) {
         const double cpk = (a[0] + T * (a[1] + T * (a[2] + T * (a[3] + a[4] * T)))) * kR * md.invW[k];
         const double JTk = Wk * acc[q][1];
-        WA[k * TS] = Wk * (wd * W + acc[q][2]) / rho;
-        WB[k * TS] = Wk * acc[q][3] / rho;
+        WAB[k * TS] = make_double2(Wk * (wd * W + acc[q][2]) / rho, Wk * acc[q][3] / rho);
         JT[k * TS] = JTk;
         H[k * TS] = hk;
         redc[(N + k) * TS] = (cpk - hk / cp * dcpdT) * Wk * wd / rho + hk * JTk;
@@ -487,20 +501,37 @@ __global__ __launch_bounds__(NT) void tile_kernel(MechDev md, int64_t n, int64_t
     for (int k = g; k < N - 1; k += Gr) jac[(int64_t)((k + 1) * N) * ld + sg] = JT[k * TS];
   const double* aN = nasa_coeffs(md, N - 1, T);
   const double cpN = (aN[0] + T * (aN[1] + T * (aN[2] + T * (aN[3] + aN[4] * T)))) * kR * md.invW[N - 1];
+  const double* Xb = lds + (size_t)L.X * TS + s;
   for (int j = g; j < N - 1; j += Gr) {
+    // Column j: terms and row markers, read kColBatch records at a time with
+    // independent loads; every record is evaluated without branching (markers
+    // and padding have coef = 0) and a marker finishes the current row.
     const double vj = md.vcol[j];
-    const int* cp_ = md.col_ptr + (size_t)j * N;
-    int t = cp_[0];
+    const ColRec* rec = md.colrec + md.col_start[j];
+    const int cnt = md.col_start[j + 1] - md.col_start[j];
+    double* outp = jac + (int64_t)(N + j + 1) * ld + sg;       // element (1, j+1)
+    const int64_t rstride = (int64_t)N * ld;
     double TR = 0.0;
-    for (int k = 0; k < N; ++k) {
-      const int tend = cp_[k + 1];
-      double val = WA[k * TS] * vj + WB[k * TS];
-      for (; t < tend; ++t) {
-        const int src = md.term_src[t], x = md.term_x[t];
-        val += md.term_coef[t] * P[src * TS] * X[(x & 0xFFFF) * TS] * X[(x >> 16) * TS];
+    double2 ab = WAB[0];
+    double val = ab.x * vj + ab.y;
+    int k = 0;
+    for (int b = 0; b < cnt; b += kColBatch) {
+      ColRec r[kColBatch];
+#pragma unroll
+      for (int u = 0; u < kColBatch; ++u) r[u] = rec[b + u];
+#pragma unroll
+      for (int u = 0; u < kColBatch; ++u) {
+        const int x = r[u].x;
+        val += r[u].coef * P[r[u].src * TS] * Xb[(x & 0x7FFF) * TS] * Xb[((x >> 15) & 0x7FFF) * TS];
+        if (x & kColMark) {
+          if (k < N - 1 && live) *outp = val;
+          TR += H[k * TS] * val;
+          outp += rstride;
+          ++k;
+          ab = WAB[(k < N ? k : N - 1) * TS];
+          val = ab.x * vj + ab.y;
+        }
       }
-      if (k < N - 1 && live) jac[(int64_t)((k + 1) * N + j + 1) * ld + sg] = val;
-      TR += H[k * TS] * val;
     }
     const double* aj = nasa_coeffs(md, j, T);
     const double cpj = (aj[0] + T * (aj[1] + T * (aj[2] + T * (aj[3] + aj[4] * T)))) * kR * md.invW[j];
@@ -542,24 +573,20 @@ hipError_t launch_tile(bool jac_mode, int TS, int NT, const MechDev& md, int64_t
                        const double* phi, const double* p, double* rop_f, double* rop_r, double* pmod,
                        double* wdot, double* dphi, double* jac, size_t lds, hipStream_t st) {
   const int kpt = (md.N + NT / TS - 1) / (NT / TS);
-#define PYJAC_VARIANT(ts, nt)                                                                        \
-  if (TS == ts && NT == nt)                                                                          \
+#define PYJAC_VARIANT(ts, nt)                                                                          \
+  if (TS == ts && NT == nt)                                                                            \
     return jac_mode ? launch_k<ts, nt, true>(kpt, md, n, ld, phi, p, rop_f, rop_r, pmod, wdot, dphi, jac, lds, st) \
                     : launch_k<ts, nt, false>(kpt, md, n, ld, phi, p, rop_f, rop_r, pmod, wdot, dphi, jac, lds, st);
-  PYJAC_VARIANT(16, 256)
-  PYJAC_VARIANT(16, 512)
   PYJAC_VARIANT(16, 1024)
-  PYJAC_VARIANT(8, 256)
+  PYJAC_VARIANT(16, 512)
+  PYJAC_VARIANT(32, 1024)
+  PYJAC_VARIANT(64, 1024)
   PYJAC_VARIANT(8, 512)
   PYJAC_VARIANT(8, 1024)
-  PYJAC_VARIANT(4, 256)
   PYJAC_VARIANT(4, 512)
   PYJAC_VARIANT(4, 1024)
   PYJAC_VARIANT(2, 512)
   PYJAC_VARIANT(2, 1024)
-  PYJAC_VARIANT(32, 512)
-  PYJAC_VARIANT(32, 1024)
-  PYJAC_VARIANT(64, 1024)
 #undef PYJAC_VARIANT
   return hipErrorInvalidValue;
 }

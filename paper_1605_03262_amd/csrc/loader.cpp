@@ -309,82 +309,76 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
     const double lnpr = std::log(kOneAtm / kGasConstant);
     int ng = 0;
-    P.eff_ptr.push_back(0);
-    P.plog_ptr.push_back(0);
     for (int slot = 0; slot < NR; ++slot) {
       const RawRxn& r = m.rxn[order[slot]];
+      RxnRec rec;
+      std::memset(&rec, 0, sizeof(rec));
       int info = r.cls | (r.blend << 4) | (r.rev << 8) | (r.coll << 12);
       for (auto& q : r.reac) if (q.first == N - 1) info |= F_LAST_SPECIES;
       for (auto& q : r.prod) if (q.first == N - 1) info |= F_LAST_SPECIES;
       if (r.blend == B_TROE && r.troe.size() == 4) info |= F_TROE_T2;
-      P.rinfo.push_back(info);
-      P.rorig.push_back(r.file_index);
+      rec.info = info;
+      rec.orig = r.file_index;
       int sf = 0, sr = 0;
       for (int q = 0; q < kMaxSide; ++q) {
-        P.side.push_back(q < (int)r.reac.size() ? pack_side(r.reac[q].first, r.reac[q].second) : -1);
+        rec.side[q] = q < (int)r.reac.size() ? pack_side(r.reac[q].first, r.reac[q].second) : -1;
         if (q < (int)r.reac.size()) sf += r.reac[q].second;
-      }
-      for (int q = 0; q < kMaxSide; ++q) {
-        P.side.push_back(q < (int)r.prod.size() ? pack_side(r.prod[q].first, r.prod[q].second) : -1);
+        rec.side[kMaxSide + q] = q < (int)r.prod.size() ? pack_side(r.prod[q].first, r.prod[q].second) : -1;
         if (q < (int)r.prod.size()) sr += r.prod[q].second;
       }
-      P.sum_f.push_back(sf);
-      P.sum_r.push_back(sr);
+      rec.sum_f = sf;
+      rec.sum_r = sr;
       std::map<int, int> netnu;
       for (auto& q : r.reac) netnu[q.first] -= q.second;
       for (auto& q : r.prod) netnu[q.first] += q.second;
       int dnu = 0, c = 0;
       for (auto& [k, nu] : netnu) {
         if (!nu) continue;
-        P.net.push_back(pack_side(k, nu & 0xFFFF));
+        rec.net[c++] = pack_side(k, nu & 0xFFFF);
         dnu += nu;
-        ++c;
       }
-      for (; c < kMaxNet; ++c) P.net.push_back(-1);
-      P.dnu_lnpr.push_back(dnu * lnpr);
+      for (; c < kMaxNet; ++c) rec.net[c] = -1;
+      rec.dnu_lnpr = dnu * lnpr;
       // Arrhenius: primary rate coefficient (k_f), secondary ratio k0/kinf, reverse
-      double a9[kArrStride] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-      if (r.cls == K_ELEM || r.cls == K_THD) { a9[0] = r.arr.A; a9[1] = r.arr.b; a9[2] = r.arr.Ta; }
+      if (r.cls == K_ELEM || r.cls == K_THD) { rec.arr[0] = r.arr.A; rec.arr[1] = r.arr.b; rec.arr[2] = r.arr.Ta; }
       if (r.cls == K_FALLOFF || r.cls == K_CHEMACT) {
         const Arrh& pri = (r.cls == K_FALLOFF) ? r.high : r.low;
-        a9[0] = pri.A; a9[1] = pri.b; a9[2] = pri.Ta;
-        a9[3] = r.low.A / r.high.A; a9[4] = r.low.b - r.high.b; a9[5] = r.low.Ta - r.high.Ta;
+        rec.arr[0] = pri.A; rec.arr[1] = pri.b; rec.arr[2] = pri.Ta;
+        rec.arr[3] = r.low.A / r.high.A; rec.arr[4] = r.low.b - r.high.b; rec.arr[5] = r.low.Ta - r.high.Ta;
       }
-      if (r.rev == R_EXPLICIT) { a9[6] = r.revr.A; a9[7] = r.revr.b; a9[8] = r.revr.Ta; }
-      for (double v : a9) P.arr.push_back(v);
-      double f5[kFparStride] = {0, 0, 0, 0, 0};
-      if (r.blend == B_TROE) for (size_t q = 0; q < r.troe.size(); ++q) f5[q] = r.troe[q];
+      if (r.rev == R_EXPLICIT) { rec.arr[6] = r.revr.A; rec.arr[7] = r.revr.b; rec.arr[8] = r.revr.Ta; }
+      if (r.blend == B_TROE) for (size_t q = 0; q < r.troe.size(); ++q) rec.fpar[q] = r.troe[q];
       if (r.blend == B_SRI) {
-        f5[0] = r.sri[0]; f5[1] = r.sri[1]; f5[2] = r.sri[2];
-        f5[3] = r.sri.size() > 3 ? r.sri[3] : 1.0;
-        f5[4] = r.sri.size() > 4 ? r.sri[4] : 0.0;
+        rec.fpar[0] = r.sri[0]; rec.fpar[1] = r.sri[1]; rec.fpar[2] = r.sri[2];
+        rec.fpar[3] = r.sri.size() > 3 ? r.sri[3] : 1.0;
+        rec.fpar[4] = r.sri.size() > 4 ? r.sri[4] : 0.0;
       }
-      for (double v : f5) P.fpar.push_back(v);
       // collider
-      P.coll_m.push_back(r.coll == C_SPECIES ? r.m : -1);
+      rec.coll_m = (r.coll == C_SPECIES) ? r.m : -1;
       double aN = 1.0;
       if (r.coll == C_EFF) {
+        rec.aux0 = (int)P.eff_sp.size();
         for (auto& [k, a] : r.eff) {
           if (a == 1.0) continue;
           P.eff_sp.push_back(k);
           P.eff_am1.push_back(a - 1.0);
           if (k == N - 1) aN = a;
         }
+        rec.aux1 = (int)P.eff_sp.size();
       }
-      P.eff_ptr.push_back((int)P.eff_sp.size());
-      P.alphaN_m1.push_back(aN - 1.0);
+      rec.alphaN_m1 = aN - 1.0;
       bool has_g = (r.coll == C_EFF) || (r.coll == C_SPECIES);
-      P.gslot.push_back(has_g ? ng++ : -1);
-      // PLOG
+      rec.gslot = has_g ? ng++ : -1;
       if (r.cls == K_PLOG) {
         auto pts = r.plog;
         std::sort(pts.begin(), pts.end(), [](const std::array<double, 4>& a, const std::array<double, 4>& b) { return a[0] < b[0]; });
+        rec.aux0 = (int)P.plog.size() / 4;
         for (auto& q : pts) { P.plog.push_back(std::log(q[0])); P.plog.push_back(std::log(q[1])); P.plog.push_back(q[2]); P.plog.push_back(q[3]); }
+        rec.aux1 = (int)P.plog.size() / 4;
       }
-      P.plog_ptr.push_back((int)P.plog.size() / 4);
       // Chebyshev: T~ = c1/T + c0, p~ = pc1 log10(p) + pc0
       if (r.cls == K_CHEB) {
-        P.cheb_off.push_back((int)P.cheb.size());
+        rec.aux0 = (int)P.cheb.size();
         double iTmin = 1.0 / r.Tmin, iTmax = 1.0 / r.Tmax;
         double lpmin = std::log10(r.Pmin), lpmax = std::log10(r.Pmax);
         P.cheb.push_back(r.nT);
@@ -394,7 +388,8 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
         P.cheb.push_back(2.0 / (lpmax - lpmin));
         P.cheb.push_back(-(lpmin + lpmax) / (lpmax - lpmin));
         for (double v : r.eta) P.cheb.push_back(v);
-      } else P.cheb_off.push_back(-1);
+      }
+      P.rx.push_back(rec);
     }
     P.NG = ng;
     if (P.cheb.empty()) P.cheb.push_back(0.0);
@@ -411,11 +406,11 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
     }
     P.spg_ptr.push_back(0);
     for (int k = 0; k < N; ++k) {
-      for (auto& e : lists[k]) { P.spg_rxn.push_back(e.first); P.spg_nu.push_back(e.second); }
-      P.spg_ptr.push_back((int)P.spg_rxn.size());
+      for (auto& e : lists[k]) P.spg_ent.push_back(e.first | ((int)e.second << 16));
+      P.spg_ptr.push_back((int)P.spg_ent.size());
     }
-    if (P.spg_rxn.empty()) { P.spg_rxn.push_back(0); P.spg_nu.push_back(0.0); }
-    // ---- Jacobian column terms.  For species row k and species column j the
+    P.spg_ent.resize(P.spg_ent.size() + 4, 0);      // slack for the unrolled gather
+    // ---- Jacobian column streams.  For species row k and species column j the
     // j-specific part of J[k+1][j+1] is sum_t coef_t * P[src_t] * X[x1_t] * X[x2_t]
     // with P = {c_i k_f,i (slots 0..NR-1), c_i k_r,i (NR..2NR-1), dc_i/dE_i * R_i (2NR..)}.
     struct Term { int j, k, src, x; double coef; };
@@ -430,7 +425,7 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
           mol.push_back(q.first);
         }
       while (mol.size() < 2) mol.push_back(N);
-      return mol[0] | (mol[1] << 16);
+      return mol[0] | (mol[1] << 15);
     };
     for (int slot = 0; slot < NR; ++slot) {
       const RawRxn& r = m.rxn[order[slot]];
@@ -450,36 +445,38 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
             if (l == N - 1) continue;
             terms.push_back({l, k, NR + slot, cofactors(r.prod, l), -m.W[k] / m.W[l] * nu_k * q.second});
           }
-        int g = P.gslot[slot];
+        int g = P.rx[slot].gslot;
         if (r.coll == C_EFF) {
           for (auto& [l, a] : r.eff) {
             if (l == N - 1 || a == 1.0) continue;
-            terms.push_back({l, k, 2 * NR + g, N | (N << 16), m.W[k] / m.W[l] * nu_k * (a - 1.0)});
+            terms.push_back({l, k, 2 * NR + g, N | (N << 15), m.W[k] / m.W[l] * nu_k * (a - 1.0)});
           }
         } else if (r.coll == C_SPECIES && r.m != N - 1) {
-          terms.push_back({r.m, k, 2 * NR + g, N | (N << 16), m.W[k] / m.W[r.m] * nu_k});
+          terms.push_back({r.m, k, 2 * NR + g, N | (N << 15), m.W[k] / m.W[r.m] * nu_k});
         }
       }
     }
     std::stable_sort(terms.begin(), terms.end(), [](const Term& a, const Term& b) {
       return a.j != b.j ? a.j < b.j : a.k < b.k;
     });
-    P.col_ptr.assign((size_t)(N - 1) * N + 1, 0);
+
     {
       size_t t = 0;
-      for (int j = 0; j < N - 1; ++j)
+      for (int j = 0; j < N - 1; ++j) {
+        P.col_start.push_back((int)P.colrec.size());
         for (int k = 0; k < N; ++k) {
-          P.col_ptr[(size_t)j * N + k] = (int)t;
           while (t < terms.size() && terms[t].j == j && terms[t].k == k) {
-            P.term_src.push_back(terms[t].src);
-            P.term_x.push_back(terms[t].x);
-            P.term_coef.push_back(terms[t].coef);
+            P.colrec.push_back(ColRec{terms[t].coef, terms[t].src, terms[t].x});
             ++t;
           }
+          // end of row k; src -1 addresses X[N] = 1 (the LDS row just below P),
+          // so markers and padding always contribute exactly 0
+          P.colrec.push_back(ColRec{0.0, -1, N | (N << 15) | kColMark});
         }
-      P.col_ptr[(size_t)(N - 1) * N] = (int)t;
+        while (P.colrec.size() % kColBatch) P.colrec.push_back(ColRec{0.0, -1, N | (N << 15)});
+      }
+      P.col_start.push_back((int)P.colrec.size());
     }
-    if (P.term_src.empty()) { P.term_src.push_back(0); P.term_x.push_back(0); P.term_coef.push_back(0.0); }
     return PYJAC_OK;
   } catch (const LoadError& e) {
     msg = e.what();
@@ -488,6 +485,21 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
     msg = e.what();
     return PYJAC_E_PARSE;
   }
+}
+
+std::vector<int> species_chunk_bounds(const PackedMech& P, int chunk) {
+  const int N = P.N;
+  const int nch = (P.NR + chunk - 1) / chunk;
+  std::vector<int> b((size_t)(nch + 1) * N);
+  for (int k = 0; k < N; ++k) {
+    int e = P.spg_ptr[k];
+    for (int c = 0; c <= nch; ++c) {
+      const int lim = c * chunk;
+      while (e < P.spg_ptr[k + 1] && (P.spg_ent[e] & 0xFFFF) < lim) ++e;
+      b[(size_t)c * N + k] = e;
+    }
+  }
+  return b;
 }
 
 }  // namespace pyjac

@@ -1,23 +1,524 @@
-// Batched Newton-matrix solves (I - h gamma J) x = b.  Placeholder entry
-// points until the solvers land; they report PYJAC_E_UNSUPPORTED.
+// Batched solves of the Newton matrix of an implicit integrator step,
+// (I - h gamma J) x = b, for every state of a batch (gfx950).
+//
+//  form      : A = I - h gamma J, transposed from the element-major,
+//              state-fastest Jacobian into one contiguous row-major N x N
+//              matrix per state (FP64 or FP32), through an LDS tile so both
+//              the reads and the writes are coalesced.
+//  lu        : one workgroup per state; right-looking LU with partial
+//              pivoting in panels of 16 columns.  The panel is factored in
+//              LDS, the row interchanges are applied to the other columns,
+//              U12 = L11^-1 A12 is formed in LDS and the trailing matrix is
+//              updated with 16x16x4 matrix-core instructions (FP32 or FP64).
+//  solve     : one wavefront per state; P b, unit-lower and upper
+//              triangular solves by row dot products.
+//  residual  : r = b - (I - h gamma J) x in FP64, one thread per state,
+//              straight from the state-fastest Jacobian (coalesced).
+// Mode 1 (mixed) factors in FP32, refines in FP64 and re-solves the states
+// that do not converge with the FP64 path (compacted list, device-side).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+#include <cstdint>
 #include <string>
 
 #include "../../include/pyjac.h"
+#include "tables.hpp"
 
 namespace pyjac {
 pyjac_status fail(pyjac_status code, const std::string& msg);
+int mech_device(const pyjac_mech* m);
+int mech_species(const pyjac_mech* m);
+
+namespace {
+
+constexpr int NB = 16;           // panel width
+constexpr int LU_THREADS = 256;  // 4 wavefronts per state
+constexpr int ST_UNSET = -100;   // internal per-state status before convergence
+constexpr int ST_SING32 = -4;    // zero pivot in the FP32 factor: re-solved in FP64
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- form
+// grid: (ceil(n/16), ceil(N*N/64)); 256 threads: tile of 64 elements x 16 states
+template <typename T>
+__global__ __launch_bounds__(256) void form_kernel(int N, int64_t n, int64_t ld, const double* __restrict__ jac,
+                                                   const double* __restrict__ h, double gamma,
+                                                   T* __restrict__ A, const int* __restrict__ list,
+                                                   const int* __restrict__ count, int* __restrict__ status) {
+  __shared__ T tile[64][17];
+  const int tid = threadIdx.x;
+  const int64_t NN = (int64_t)N * N;
+  const int64_t e0 = (int64_t)blockIdx.y * 64;
+  const int64_t s0 = (int64_t)blockIdx.x * 16;
+  const int64_t lim = count ? *count : n;
+  // load: lanes state-fastest
+  {
+    const int s = tid % 16;
+    const int64_t slot = s0 + s;
+    const bool ok = slot < lim;
+    const int64_t st = ok ? (list ? list[slot] : slot) : 0;
+    const double hg = ok ? h[st] * gamma : 0.0;
+    for (int r = tid / 16; r < 64; r += 16) {
+      const int64_t e = e0 + r;
+      T v = T(0);
+      if (ok && e < NN) {
+        const double jv = jac[e * ld + st];
+        const int64_t i = e / N, j = e % N;
+        const double a = (i == j ? 1.0 : 0.0) - hg * jv;
+        if (!isfinite(a)) status[st] = -3;
+        v = (T)a;
+      }
+      tile[r][s] = v;
+    }
+  }
+  __syncthreads();
+  // store: lanes element-fastest, one contiguous row-major matrix per state
+  {
+    const int r = tid % 64;
+    for (int s = tid / 64; s < 16; s += 4) {
+      const int64_t slot = s0 + s, e = e0 + r;
+      if (slot < lim && e < NN) A[slot * NN + e] = tile[r][s];
+    }
+  }
 }
+
+template <typename T> struct Mfma;
+// 16x16x4 matrix-core products.  Both precisions take A[row = lane % 16][k =
+// lane / 16] and B[k = lane / 16][col = lane % 16]; the result slot v of lane
+// l holds column l % 16 and row row(l / 16, v), which differs between the FP32
+// and the FP64 instruction (checked on gfx950 with one-hot operands).
+template <> struct Mfma<float> {
+  typedef floatx4 acc_t;
+  __device__ static acc_t run(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int q, int v) { return 4 * q + v; }
+};
+template <> struct Mfma<double> {
+  typedef doublex4 acc_t;
+  __device__ static acc_t run(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int q, int v) { return q + 4 * v; }
+};
+
+// ---------------------------------------------------------------- LU
+// One workgroup per (listed) state.  A: row-major N x N per slot; piv: N per slot.
+// LDS: panel Pn[N][NB+1], U12 U[NB][N+1], reduction scratch.
+template <typename T>
+__global__ __launch_bounds__(LU_THREADS) void lu_kernel(int N, int64_t n, T* __restrict__ Aall,
+                                                        int* __restrict__ pivall, const int* __restrict__ list,
+                                                        const int* __restrict__ count, int* __restrict__ status,
+                                                        int sing_code) {
+  extern __shared__ char smem[];
+  const int64_t slot = blockIdx.x;
+  const int64_t lim = count ? *count : n;
+  if (slot >= lim) return;
+  const int64_t st = list ? list[slot] : slot;
+  if (status[st] == -3) return;
+  T* A = Aall + slot * (int64_t)N * N;
+  int* piv = pivall + slot * (int64_t)N;
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int PS = NB + 1, US = N + 1;
+  T* Pn = reinterpret_cast<T*>(smem);                       // N * PS
+  T* U = Pn + (size_t)N * PS;                               // NB * US
+  T* redv = U + (size_t)NB * US;                            // LU_THREADS
+  int* redi = reinterpret_cast<int*>(redv + LU_THREADS);    // LU_THREADS
+  __shared__ int singular;
+  if (tid == 0) singular = 0;
+  for (int k0 = 0; k0 < N; k0 += NB) {
+    const int nb = min(NB, N - k0), M = N - k0, W = N - k0 - nb;
+    // 1. panel to LDS
+    for (int e = tid; e < M * nb; e += LU_THREADS) {
+      const int r = e / nb, c = e % nb;
+      Pn[r * PS + c] = A[(int64_t)(k0 + r) * N + k0 + c];
+    }
+    __syncthreads();
+    // 2. factor the panel with partial pivoting
+    for (int c = 0; c < nb; ++c) {
+      T best = T(-1);
+      int bi = c;
+      for (int r = c + tid; r < M; r += LU_THREADS) {
+        const T v = fabs(Pn[r * PS + c]);
+        if (v > best) { best = v; bi = r; }
+      }
+      redv[tid] = best;
+      redi[tid] = bi;
+      __syncthreads();
+      for (int w = LU_THREADS / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+          const T a = redv[tid], b = redv[tid + w];
+          const int ia = redi[tid], ib = redi[tid + w];
+          if (b > a || (b == a && ib < ia)) { redv[tid] = b; redi[tid] = ib; }
+        }
+        __syncthreads();
+      }
+      const int pr = redi[0];
+      const T pmax = redv[0];
+      if (tid == 0) {
+        piv[k0 + c] = k0 + pr;
+        if (!(pmax > T(0))) singular = 1;
+      }
+      if (pr != c && tid < nb) {
+        const T t = Pn[c * PS + tid];
+        Pn[c * PS + tid] = Pn[pr * PS + tid];
+        Pn[pr * PS + tid] = t;
+      }
+      __syncthreads();
+      const T d = Pn[c * PS + c];
+      const T inv = d != T(0) ? T(1) / d : T(0);
+      for (int r = c + 1 + tid; r < M; r += LU_THREADS) {
+        const T l = Pn[r * PS + c] * inv;
+        Pn[r * PS + c] = l;
+        for (int cc = c + 1; cc < nb; ++cc) Pn[r * PS + cc] -= l * Pn[c * PS + cc];
+      }
+      __syncthreads();
+    }
+    // 3. panel back to global
+    for (int e = tid; e < M * nb; e += LU_THREADS) {
+      const int r = e / nb, c = e % nb;
+      A[(int64_t)(k0 + r) * N + k0 + c] = Pn[r * PS + c];
+    }
+    // 4. row interchanges on the columns outside the panel (sequential in c)
+    for (int c = 0; c < nb; ++c) {
+      const int pr = piv[k0 + c];
+      if (pr != k0 + c) {
+        for (int col = tid; col < N - nb; col += LU_THREADS) {
+          const int cc = col < k0 ? col : col + nb;
+          const T t = A[(int64_t)(k0 + c) * N + cc];
+          A[(int64_t)(k0 + c) * N + cc] = A[(int64_t)pr * N + cc];
+          A[(int64_t)pr * N + cc] = t;
+        }
+      }
+      __syncthreads();
+    }
+    if (W <= 0) break;
+    // 5. U12 = L11^-1 A12 (unit lower), in LDS, then back to global
+    for (int e = tid; e < nb * W; e += LU_THREADS) {
+      const int r = e / W, c = e % W;
+      U[r * US + c] = A[(int64_t)(k0 + r) * N + k0 + nb + c];
+    }
+    __syncthreads();
+    for (int c = tid; c < W; c += LU_THREADS) {
+      for (int r = 1; r < nb; ++r) {
+        T acc = U[r * US + c];
+        for (int t = 0; t < r; ++t) acc -= Pn[r * PS + t] * U[t * US + c];
+        U[r * US + c] = acc;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < nb * W; e += LU_THREADS) {
+      const int r = e / W, c = e % W;
+      A[(int64_t)(k0 + r) * N + k0 + nb + c] = U[r * US + c];
+    }
+    // 6. trailing update A22 -= L21 U12 on the matrix cores, 16x16 tiles
+    const int tr = (W + 15) / 16;
+    const int row = lane % 16, kq = lane / 16;
+    for (int t = wave; t < tr * tr; t += LU_THREADS / 64) {
+      const int r0 = (t / tr) * 16, c0 = (t % tr) * 16;
+      typename Mfma<T>::acc_t acc;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rr = r0 + Mfma<T>::row(kq, i), cc = c0 + row;
+        acc[i] = (rr < W && cc < W) ? A[(int64_t)(k0 + nb + rr) * N + k0 + nb + cc] : T(0);
+      }
+#pragma unroll
+      for (int kk = 0; kk < NB; kk += 4) {
+        const int ar = r0 + row, bc = c0 + row, kx = kk + kq;
+        const T a = (ar < W && kx < nb) ? -Pn[(nb + ar) * PS + kx] : T(0);
+        const T b = (bc < W && kx < nb) ? U[kx * US + bc] : T(0);
+        acc = Mfma<T>::run(a, b, acc);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rr = r0 + Mfma<T>::row(kq, i), cc = c0 + row;
+        if (rr < W && cc < W) A[(int64_t)(k0 + nb + rr) * N + k0 + nb + cc] = acc[i];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && singular) status[st] = sing_code;
+}
+
+// ---------------------------------------------------------------- solve
+// One wavefront per (listed) state, 4 states per 256-thread block; waves
+// without work stay in the block and only skip the memory operations, so
+// every barrier is reached by all four.
+// direct: x = A^-1 b, b from rhs [N][ld], x to xout [N][ld].
+// refine: d = A^-1 r with r from rbuf [N][n]; x += d in xs [N][n] (FP64) and
+//   the state converges at this sweep when ||d||_inf <= rtol ||x||_inf.
+template <typename T, bool REFINE>
+__global__ __launch_bounds__(256) void solve_kernel(int N, int64_t n, int64_t ld, const T* __restrict__ Aall,
+                                                    const int* __restrict__ pivall, const double* __restrict__ rhs,
+                                                    const double* __restrict__ rbuf, double* __restrict__ xs,
+                                                    double* __restrict__ xout, const int* __restrict__ list,
+                                                    const int* __restrict__ count, int* __restrict__ status,
+                                                    int sweep, double rtol) {
+  extern __shared__ char smem[];
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const int64_t slot = (int64_t)blockIdx.x * 4 + wv;
+  const int64_t lim = count ? *count : n;
+  bool active = slot < lim;
+  const int64_t st = active ? (list ? list[slot] : slot) : 0;
+  const int s0 = active ? status[st] : 0;
+  active = active && (REFINE ? s0 == ST_UNSET : (s0 != -3 && s0 != -1 && s0 != ST_SING32));
+  T* y = reinterpret_cast<T*>(smem) + (size_t)wv * N;
+  const T* A = Aall + (active ? slot : 0) * (int64_t)N * N;
+  const int* piv = pivall + (active ? slot : 0) * (int64_t)N;
+  if (active)
+    for (int i = lane; i < N; i += 64) y[i] = REFINE ? (T)rbuf[(int64_t)i * n + st] : (T)rhs[(int64_t)i * ld + st];
+  __syncthreads();
+  if (active && lane == 0)
+    for (int i = 0; i < N; ++i) {
+      const int p = piv[i];
+      if (p != i) { T t = y[i]; y[i] = y[p]; y[p] = t; }
+    }
+  __syncthreads();
+  for (int i = 1; i < N; ++i) {            // unit lower
+    T acc = T(0);
+    if (active)
+      for (int j = lane; j < i; j += 64) acc += A[(int64_t)i * N + j] * y[j];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (active && lane == 0) y[i] -= acc;
+    __syncthreads();
+  }
+  for (int i = N - 1; i >= 0; --i) {       // upper
+    T acc = T(0);
+    if (active)
+      for (int j = i + 1 + lane; j < N; j += 64) acc += A[(int64_t)i * N + j] * y[j];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (active && lane == 0) y[i] = (y[i] - acc) / A[(int64_t)i * N + i];
+    __syncthreads();
+  }
+  if (!active) return;
+  if (!REFINE) {
+    bool fin = true;
+    for (int i = lane; i < N; i += 64) {
+      xout[(int64_t)i * ld + st] = (double)y[i];
+      fin = fin && isfinite((double)y[i]);
+    }
+    fin = __all(fin);
+    if (lane == 0 && s0 == ST_UNSET) status[st] = fin ? 0 : -1;
+    return;
+  }
+  double dmax = 0.0, xmax = 0.0;
+  bool fin = true;
+  for (int i = lane; i < N; i += 64) {
+    const double d = (double)y[i];
+    const double xv = xs[(int64_t)i * n + st] + d;
+    xs[(int64_t)i * n + st] = xv;
+    dmax = fmax(dmax, fabs(d));
+    xmax = fmax(xmax, fabs(xv));
+    fin = fin && isfinite(xv);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    dmax = fmax(dmax, __shfl_xor(dmax, o));
+    xmax = fmax(xmax, __shfl_xor(xmax, o));
+  }
+  fin = __all(fin);
+  if (lane == 0 && sweep > 0 && fin && dmax <= rtol * xmax) status[st] = sweep;
+}
+
+// r = b - (I - h gamma J) x in FP64, one thread per state, rows in blocks of
+// 8 so each x_j load serves 8 multiply-adds; every load is coalesced across
+// the states of a wavefront.  Converged states are skipped.
+__global__ __launch_bounds__(256) void residual_kernel(int N, int64_t n, int64_t ld, const double* __restrict__ jac,
+                                                       const double* __restrict__ h, double gamma,
+                                                       const double* __restrict__ rhs, const double* __restrict__ xs,
+                                                       double* __restrict__ rbuf, const int* __restrict__ status) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n || status[s] != ST_UNSET) return;
+  const double hg = h[s] * gamma;
+  constexpr int IB = 8;
+  for (int i0 = 0; i0 < N; i0 += IB) {
+    double acc[IB];
+#pragma unroll
+    for (int u = 0; u < IB; ++u) acc[u] = 0.0;
+    for (int j = 0; j < N; ++j) {
+      const double xj = xs[(int64_t)j * n + s];
+#pragma unroll
+      for (int u = 0; u < IB; ++u)
+        if (i0 + u < N) acc[u] += jac[((int64_t)(i0 + u) * N + j) * ld + s] * xj;
+    }
+#pragma unroll
+    for (int u = 0; u < IB; ++u) {
+      const int i = i0 + u;
+      if (i < N) rbuf[(int64_t)i * n + s] = rhs[(int64_t)i * ld + s] - (xs[(int64_t)i * n + s] - hg * acc[u]);
+    }
+  }
+}
+
+__global__ void init_status_kernel(int64_t n, int* __restrict__ status, double* __restrict__ xs, int N) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  status[s] = ST_UNSET;
+  if (xs)
+    for (int i = 0; i < N; ++i) xs[(int64_t)i * n + s] = 0.0;
+}
+
+__global__ void copy_rhs_kernel(int N, int64_t n, int64_t ld, const double* __restrict__ rhs, double* __restrict__ rbuf) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  for (int i = 0; i < N; ++i) rbuf[(int64_t)i * n + s] = rhs[(int64_t)i * ld + s];
+}
+
+// States that did not converge (status still unset) go to the FP64 list.
+// The list order depends on scheduling; each listed state is solved on its
+// own, so results do not depend on that order.
+__global__ void compact_kernel(int64_t n, const int* __restrict__ status, int* __restrict__ list, int* __restrict__ count) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  if (status[s] == ST_UNSET || status[s] == ST_SING32) {
+    const int at = atomicAdd(count, 1);
+    list[at] = (int)s;
+  }
+}
+
+__global__ void finish_kernel(int N, int64_t n, int64_t ld, const int* __restrict__ status,
+                              const double* __restrict__ xs, double* __restrict__ xout, int* __restrict__ info,
+                              const int* __restrict__ fb_status, int mode) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  int st = status[s];
+  if (mode == 1) {
+    if (st >= 0 && xs)
+      for (int i = 0; i < N; ++i) xout[(int64_t)i * ld + s] = xs[(int64_t)i * n + s];
+    if (st == ST_UNSET || st == ST_SING32) st = (fb_status[s] == 0) ? -2 : fb_status[s];   // FP64 re-solve
+  }
+  info[s] = st;
+}
+
+__global__ void zero_int_kernel(int* p) { *p = 0; }
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct WsLayout {
+  size_t a32 = 0, a64 = 0, piv = 0, status = 0, fbstatus = 0, xs = 0, rbuf = 0, list = 0, count = 0, total = 0;
+};
+
+WsLayout ws_layout(int N, int64_t n, int mode) {
+  WsLayout L;
+  size_t off = 0;
+  const size_t NN = (size_t)N * N;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  if (mode == 1) L.a32 = take((size_t)n * NN * sizeof(float));
+  L.a64 = take((size_t)n * NN * sizeof(double));
+  L.piv = take((size_t)n * N * sizeof(int));
+  L.status = take((size_t)n * sizeof(int));
+  L.fbstatus = take((size_t)n * sizeof(int));
+  if (mode == 1) {
+    L.xs = take((size_t)n * N * sizeof(double));
+    L.rbuf = take((size_t)n * N * sizeof(double));
+    L.list = take((size_t)n * sizeof(int));
+    L.count = take(sizeof(int));
+  }
+  L.total = off;
+  return L;
+}
+
+size_t lu_lds(int N, size_t elem) { return ((size_t)N * (NB + 1) + (size_t)NB * (N + 1) + LU_THREADS) * elem + LU_THREADS * sizeof(int); }
+
+template <typename T>
+hipError_t run_direct(int N, int64_t n, int64_t ld, const double* jac, const double* h, double gamma,
+                      const double* rhs, double* x, T* A, int* piv, const int* list, const int* count, int* status,
+                      hipStream_t st) {
+  dim3 fg((unsigned)((n + 15) / 16), (unsigned)(((int64_t)N * N + 63) / 64));
+  hipLaunchKernelGGL(form_kernel<T>, fg, dim3(256), 0, st, N, n, ld, jac, h, gamma, A, list, count, status);
+  const size_t lds = lu_lds(N, sizeof(T));
+  hipError_t e = hipFuncSetAttribute((const void*)lu_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(lu_kernel<T>, dim3((unsigned)n), dim3(LU_THREADS), lds, st, N, n, A, piv, list, count, status, -1);
+  hipLaunchKernelGGL((solve_kernel<T, false>), dim3((unsigned)((n + 3) / 4)), dim3(256), 4 * N * sizeof(T), st, N, n, ld,
+                     (const T*)A, (const int*)piv, rhs, (const double*)nullptr, (double*)nullptr, x, list, count, status, 0,
+                     0.0);
+  return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace pyjac
+
+using namespace pyjac;
 
 extern "C" {
 
-size_t pyjac_newton_workspace_bytes(const pyjac_mech*, int64_t, int32_t) { return 0; }
+size_t pyjac_newton_workspace_bytes(const pyjac_mech* m, int64_t n, int32_t mode) {
+  if (!m || n < 0 || (mode != 0 && mode != 1)) return 0;
+  return ws_layout(mech_species(m), n, mode).total;
+}
 
-pyjac_status pyjac_newton_factor_solve(const pyjac_mech*, int64_t, int64_t, const double*, const double*,
-                                       double, const double*, double*, int32_t, int32_t, double, int32_t*,
-                                       void*, size_t, void*) {
-  return pyjac::fail(PYJAC_E_UNSUPPORTED, "Newton solver not built yet");
+pyjac_status pyjac_newton_factor_solve(const pyjac_mech* m, int64_t n, int64_t ld, const double* jac, const double* h,
+                                       double gamma, const double* rhs, double* x, int32_t mode, int32_t max_refine,
+                                       double rtol, int32_t* info, void* workspace, size_t workspace_bytes,
+                                       void* stream) {
+  if (!m) return fail(PYJAC_E_INVALID, "mechanism handle is NULL");
+  if (n < 0 || ld < n) return fail(PYJAC_E_INVALID, "bad n_states / ld");
+  if (mode != 0 && mode != 1) return fail(PYJAC_E_INVALID, "mode must be 0 or 1");
+  if (mode == 1 && (max_refine < 1 || max_refine > 100 || !(rtol > 0))) return fail(PYJAC_E_INVALID, "bad max_refine / rtol");
+  if (n == 0) return PYJAC_OK;
+  if (!jac || !h || !rhs || !x || !info) return fail(PYJAC_E_INVALID, "NULL array argument");
+  for (const void* q : {(const void*)jac, (const void*)h, (const void*)rhs, (const void*)x})
+    if (reinterpret_cast<uintptr_t>(q) & 7u) return fail(PYJAC_E_INVALID, "pointer not 8-byte aligned");
+  if (x == rhs || x == jac) return fail(PYJAC_E_INVALID, "x may not alias rhs or jac");
+  if (n > (int64_t)1 << 30) return fail(PYJAC_E_INVALID, "n_states too large");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != mech_device(m))
+    return fail(PYJAC_E_INVALID, "current HIP device differs from the mechanism's device");
+  const int N = mech_species(m);
+  const WsLayout L = ws_layout(N, n, mode);
+  if (!workspace || workspace_bytes < L.total) return fail(PYJAC_E_WORKSPACE, "workspace smaller than pyjac_newton_workspace_bytes");
+  if (lu_lds(N, sizeof(double)) > 163840) return fail(PYJAC_E_UNSUPPORTED, "mechanism too large for the LU kernel");
+  char* w = static_cast<char*>(workspace);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int* status = reinterpret_cast<int*>(w + L.status);
+  int* fbs = reinterpret_cast<int*>(w + L.fbstatus);
+  int* piv = reinterpret_cast<int*>(w + L.piv);
+  double* A64 = reinterpret_cast<double*>(w + L.a64);
+  const unsigned g1 = (unsigned)((n + 255) / 256);
+  hipError_t e;
+  if (mode == 0) {
+    hipLaunchKernelGGL(init_status_kernel, dim3(g1), dim3(256), 0, st, n, status, (double*)nullptr, N);
+    e = run_direct<double>(N, n, ld, jac, h, gamma, rhs, x, A64, piv, nullptr, nullptr, status, st);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(finish_kernel, dim3(g1), dim3(256), 0, st, N, n, ld, (const int*)status, (const double*)nullptr,
+                         x, info, (const int*)nullptr, 0);
+      e = hipGetLastError();
+    }
+  } else {
+    float* A32 = reinterpret_cast<float*>(w + L.a32);
+    double* xs = reinterpret_cast<double*>(w + L.xs);
+    double* rbuf = reinterpret_cast<double*>(w + L.rbuf);
+    int* list = reinterpret_cast<int*>(w + L.list);
+    int* count = reinterpret_cast<int*>(w + L.count);
+    hipLaunchKernelGGL(init_status_kernel, dim3(g1), dim3(256), 0, st, n, status, xs, N);
+    hipLaunchKernelGGL(copy_rhs_kernel, dim3(g1), dim3(256), 0, st, N, n, ld, rhs, rbuf);
+    dim3 fg((unsigned)((n + 15) / 16), (unsigned)(((int64_t)N * N + 63) / 64));
+    hipLaunchKernelGGL(form_kernel<float>, fg, dim3(256), 0, st, N, n, ld, jac, h, gamma, A32, (const int*)nullptr,
+                       (const int*)nullptr, status);
+    const size_t lds = lu_lds(N, sizeof(float));
+    e = hipFuncSetAttribute((const void*)lu_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return fail(PYJAC_E_DEVICE, hipGetErrorString(e));
+    hipLaunchKernelGGL(lu_kernel<float>, dim3((unsigned)n), dim3(LU_THREADS), lds, st, N, n, A32, piv,
+                       (const int*)nullptr, (const int*)nullptr, status, ST_SING32);
+    const unsigned gs = (unsigned)((n + 3) / 4);
+    for (int sweep = 0; sweep <= max_refine; ++sweep) {
+      if (sweep > 0)
+        hipLaunchKernelGGL(residual_kernel, dim3(g1), dim3(256), 0, st, N, n, ld, jac, h, gamma, rhs, (const double*)xs,
+                           rbuf, (const int*)status);
+      hipLaunchKernelGGL((solve_kernel<float, true>), dim3(gs), dim3(256), 4 * N * sizeof(float), st, N, n, ld,
+                         (const float*)A32, (const int*)piv, (const double*)nullptr, (const double*)rbuf, xs,
+                         (double*)nullptr, (const int*)nullptr, (const int*)nullptr, status, sweep, rtol);
+    }
+    // FP64 re-solve of the states that did not converge (or whose FP32 factor was singular)
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, count);
+    hipLaunchKernelGGL(compact_kernel, dim3(g1), dim3(256), 0, st, n, (const int*)status, list, count);
+    hipLaunchKernelGGL(init_status_kernel, dim3(g1), dim3(256), 0, st, n, fbs, (double*)nullptr, N);
+    e = run_direct<double>(N, n, ld, jac, h, gamma, rhs, x, A64, piv, list, count, fbs, st);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(finish_kernel, dim3(g1), dim3(256), 0, st, N, n, ld, (const int*)status, (const double*)xs, x,
+                         info, (const int*)fbs, 1);
+      e = hipGetLastError();
+    }
+  }
+  if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("newton launch failed: ") + hipGetErrorString(e));
+  return PYJAC_OK;
 }
 
 }  // extern "C"

@@ -32,29 +32,58 @@ constexpr int kMaxSide = 3;     // distinct species per side
 constexpr int kMaxNet = 6;      // species with nonzero net coefficient
 constexpr int kArrStride = 9;   // primary (A,b,Ta), secondary (ratio A, db, dTa), reverse (A,b,Ta)
 constexpr int kFparStride = 5;
-constexpr int kSideStride = 2 * kMaxSide;   // (species, nu) pairs packed as sp | nu << 16
-constexpr int kNetStride = kMaxNet;
 
 inline int rinfo_kind(int v) { return v & 0xF; }
+
+// Everything one reaction needs, in one 256-byte record so that a lane fetches
+// it with independent wide loads before any branch (sorted reaction order).
+struct alignas(16) RxnRec {
+  int info, sum_f, sum_r, gslot;          // class/flags, sum nu', sum nu'', G slot or -1
+  int side[2 * kMaxSide];                 // reactants then products: sp | nu << 16, -1 = none
+  int net[kMaxNet];                       // sp | nu << 16 (nu signed), -1 = none
+  int coll_m, aux0, aux1, orig;           // collider species; efficiency or PLOG range or
+                                          // Chebyshev offset; file index of the reaction
+  double dnu_lnpr, alphaN_m1;             // sum(nu) ln(p_atm/R); alpha_N - 1
+  double arr[kArrStride];
+  double fpar[kFparStride];
+  double pad[6];
+};
+static_assert(sizeof(RxnRec) == 256, "RxnRec must stay 256 bytes");
+
+// One entry of a Jacobian column stream.  Every entry contributes
+// coef * P[src] * X[x & 0x7FFF] * X[(x >> 15) & 0x7FFF] to the current element
+// (coef = 0 for markers and padding, whose src = -1 addresses the constant
+// X[N] = 1 stored just below P); an entry with bit kColMark set in x ends
+// the current row.  Column j's stream holds, for rows k = 0..N-1 in order, the
+// terms of (k, j) followed by one marker, then padding to a multiple of
+// kColBatch.
+struct alignas(16) ColRec {
+  double coef;
+  int src, x;
+};
+constexpr int kColMark = 1 << 30;
+constexpr int kColBatch = 8;
 
 // Host-side packed tables (sorted reaction order).
 struct PackedMech {
   int N = 0, NR = 0, NG = 0;
   uint64_t hash = 0;
   std::vector<double> W, invW, nasa, tmid, vcol;          // species
-  std::vector<int> rinfo, rorig, side, net, coll_m, gslot, sum_f, sum_r;
-  std::vector<double> arr, fpar, dnu_lnpr, alphaN_m1;
-  std::vector<int> eff_ptr, eff_sp;
+  std::vector<RxnRec> rx;
+  std::vector<int> eff_sp;
   std::vector<double> eff_am1;
-  std::vector<int> plog_ptr;
   std::vector<double> plog;                               // (ln p, ln A, b, Ta) per point
-  std::vector<int> cheb_off;
   std::vector<double> cheb;                               // nT, nP, c1, c0, pc1, pc0, eta...
-  std::vector<int> spg_ptr, spg_rxn;                      // per-species reaction lists
-  std::vector<double> spg_nu;
-  std::vector<int> col_ptr, term_src, term_x;             // Jacobian column terms
-  std::vector<double> term_coef;
+  std::vector<int> spg_ptr, spg_ent;                      // per-species reaction lists:
+                                                          // slot | nu << 16 (nu signed)
+  std::vector<int> col_start;                             // [N] stream offsets per column
+  std::vector<ColRec> colrec;
 };
+
+// Per-chunk bounds of the species reaction lists for reaction chunks of size
+// `chunk`: entry [c * N + k] is the first list index of species k whose
+// reaction slot is >= c * chunk; there are ceil(NR / chunk) + 1 rows.
+std::vector<int> species_chunk_bounds(const PackedMech& P, int chunk);
 
 // Parse + validate + pack.  Returns 0 or a PYJAC_E_* code with msg set.
 int build_tables(const std::string& text, PackedMech& out, std::string& msg);
@@ -67,32 +96,15 @@ struct MechDev {
   const double* __restrict__ nasa;      // [N][2][7]
   const double* __restrict__ tmid;
   const double* __restrict__ vcol;      // [N-1]
-  const int* __restrict__ rinfo;
-  const int* __restrict__ rorig;
-  const int* __restrict__ side;         // [NR][6]
-  const int* __restrict__ net;          // [NR][6]
-  const int* __restrict__ coll_m;
-  const int* __restrict__ gslot;
-  const int* __restrict__ sum_f;
-  const int* __restrict__ sum_r;
-  const double* __restrict__ arr;       // [NR][9]
-  const double* __restrict__ fpar;      // [NR][5]
-  const double* __restrict__ dnu_lnpr;  // sum(nu) * ln(p_atm / R)
-  const double* __restrict__ alphaN_m1;
-  const int* __restrict__ eff_ptr;
+  const RxnRec* __restrict__ rx;        // [NR]
   const int* __restrict__ eff_sp;
   const double* __restrict__ eff_am1;
-  const int* __restrict__ plog_ptr;
   const double* __restrict__ plog;
-  const int* __restrict__ cheb_off;
   const double* __restrict__ cheb;
-  const int* __restrict__ spg_ptr;
-  const int* __restrict__ spg_rxn;
-  const double* __restrict__ spg_nu;
-  const int* __restrict__ col_ptr;      // [(N-1)*N + 1]
-  const int* __restrict__ term_src;
-  const int* __restrict__ term_x;       // x1 | x2 << 16 (index N means "1")
-  const double* __restrict__ term_coef;
+  const int* __restrict__ spg_ent;
+  const int* __restrict__ spg_chunk;    // species_chunk_bounds for the launch's chunk size
+  const int* __restrict__ col_start;    // [N]
+  const ColRec* __restrict__ colrec;
 };
 
 }  // namespace pyjac

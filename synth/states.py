@@ -43,3 +43,14 @@ def draw_newton_inputs(seed: int, n_species: int, n_states: int,
     h = np.exp(rng.uniform(np.log(h_range[0]), np.log(h_range[1]), size=n_states))
     rhs = rng.standard_normal((n_species, n_states))
     return h, np.ascontiguousarray(rhs)
+
+
+def conditioned_steps(seed: int, jac_rows: np.ndarray, c_range=(1.0, 3.0e3),
+                      gamma: float = NEWTON_GAMMA) -> np.ndarray:
+    """Per-state step h_s = c_s / (gamma ||J_s||_inf) with c_s log-uniform on
+    c_range, so that I - h gamma J stays solvable (kappa_inf roughly c^2).
+    jac_rows: absolute row sums of each state's Jacobian, shape (N, n)."""
+    rng = np.random.default_rng(seed)
+    n = jac_rows.shape[1]
+    c = np.exp(rng.uniform(np.log(c_range[0]), np.log(c_range[1]), size=n))
+    return c / (gamma * np.max(jac_rows, axis=0))
