@@ -2,13 +2,18 @@
 
 Workload: the 53-species / 325-reaction methane-shaped synthetic mechanism,
 100,000 thermochemical states resident in HBM.  One step = one pass of the hot
-path over the batch: the dense analytical Jacobian (which evaluates the rates
-internally) followed by the batched Newton solve of I - h gamma J (FP32-LU +
-FP64 refinement) when --newton is on (default).
+path over the batch: the dense analytical Jacobian (the kernel evaluates the
+rates, production rates and RHS on the way) followed by the batched Newton
+solve of I - h gamma J in mixed precision (FP32 LU on the matrix cores + FP64
+refinement), with per-state step sizes that keep the systems solvable
+(h = c / (gamma ||J||_inf), c log-uniform on [1, 3e3]).
 
-Prints one JSON line with the Jacobian throughput, the roofline position of the
-Jacobian kernel (HIP-event timing on its launch stream), the Newton and serving
-figures, and the oracle's CPU throughput on a bounded sample.
+The JSON line also carries: the roofline position of the Jacobian kernel
+(HIP events on its launch stream), the Newton solve timed alone in both modes
+(and on the configured step sizes h ~ logU[1e-9, 1e-5] s, where the systems
+are numerically singular), a short Poisson serving run (p50/p99 latency, vs
+the plain per-request FP64 path), and the CPU oracle's throughput on a
+bounded sample.
 """
 from __future__ import annotations
 
@@ -17,6 +22,7 @@ import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -35,9 +41,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(bytes_per_launch_alg: float):
-    """HBM traffic of the Jacobian kernel from the committed rocprofv3 counter
-    summary, valid only while the kernel source is unchanged."""
+def measured_traffic():
+    """HBM bytes per launch of the Jacobian kernel from the committed rocprofv3
+    counter summary, valid only while the kernel source is unchanged."""
     path = os.path.join(ROOT, "profiles", "jacobian_c1_100k_traffic.json")
     if not os.path.exists(path):
         return None
@@ -53,27 +59,124 @@ def cpu_baseline(mech, phi, p, budget_s: float = 12.0):
     from oracle import RefMech
     ref = RefMech(text=mech.to_text())
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
-    probe = 64
+    probe = 256
     t0 = time.perf_counter()
     ref.eval_jacobian(phi[:, :probe], p[:probe], nthreads=threads)
-    dt = time.perf_counter() - t0
-    n = int(min(phi.shape[1], max(probe, budget_s / max(dt / probe, 1e-9))))
+    per_state = (time.perf_counter() - t0) / probe
+    n = phi.shape[1]
+    reps = max(1, int(budget_s / max(per_state * n, 1e-9)))
+    n_s = int(min(n, max(probe, budget_s / max(per_state, 1e-9))))
+    sub_phi, sub_p = np.ascontiguousarray(phi[:, :n_s]), p[:n_s]
     t0 = time.perf_counter()
-    ref.eval_jacobian(np.ascontiguousarray(phi[:, :n]), p[:n], nthreads=threads)
+    for _ in range(reps if n_s == n else 1):
+        ref.eval_jacobian(sub_phi, sub_p, nthreads=threads)
     dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "Jacobian evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} of the {phi.shape[1]} states, analytical Jacobian, "
+    done = n_s * (reps if n_s == n else 1)
+    return {"value": done / dt, "unit": "Jacobian evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} Jacobians ({n_s} of the {n} states"
+                      f"{', x%d passes' % reps if n_s == n and reps > 1 else ''}), "
                       f"{threads} OpenMP threads, {dt:.1f} s"}
+
+
+def time_stream(fn, reps, torch):
+    """Median and mean of `reps` runs of fn timed with HIP events on the
+    current stream (where fn launches)."""
+    import numpy as np
+    st = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(st)
+        fn()
+        b.record(st)
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    return float(np.median(ms)), float(ms.mean())
+
+
+def serving_run(n_requests: int, seed: int = 7):
+    """Poisson stream of Jacobian + mixed-Newton requests over the 13/53/111/
+    360-species mechanisms (weights 0.4/0.3/0.2/0.1), n = floor(exp(U[0, ln 4097)))
+    states each, served continuously; then the same trace through the plain
+    path (each request alone, in arrival order, FP64 LU, one stream)."""
+    import numpy as np
+    import torch
+    from paper_1605_03262_amd import NEWTON_FP64, NEWTON_MIXED, Mechanism, Server
+    from synth import NEWTON_GAMMA, config_mechanism, draw_newton_inputs, draw_states
+    rng = np.random.default_rng(seed)
+    mechs = [Mechanism(text=config_mechanism(c).to_text()) for c in range(4)]
+    reqs = []
+    for q in range(n_requests):
+        c = int(rng.choice(4, p=[0.4, 0.3, 0.2, 0.1]))
+        n = min(4096, int(np.exp(rng.uniform(0.0, np.log(4097.0)))))
+        N = mechs[c].n_species
+        phi, p = draw_states(int(rng.integers(1 << 30)), N, n, T=(800.0, 2200.0), P_atm=(1.0, 50.0),
+                             dirichlet=0.3)
+        h, b = draw_newton_inputs(int(rng.integers(1 << 30)), N, n)
+        reqs.append((c, phi, p, h, b))
+    total_states = sum(r[1].shape[1] for r in reqs)
+
+    def run_server(gaps):
+        srv = Server(hbm_budget_bytes=64 << 30, max_batch_states=16384, n_streams=4, max_refine=4)
+        ids = []
+        t0 = time.perf_counter()
+        tnext = t0
+        for (c, phi, p, h, b), gap in zip(reqs, gaps):
+            tnext += gap
+            d = tnext - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            ids.append(srv.submit(mechs[c], phi, p, h, b, NEWTON_GAMMA, mode=NEWTON_MIXED)[0])
+        lat = [srv.wait(i) for i in ids]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return np.array(lat), wall, st
+
+    # saturation: all requests at once (closed burst)
+    lat_b, wall_b, _ = run_server(np.zeros(n_requests))
+    sat_rate = n_requests / wall_b                     # requests/s at saturation
+    rate = 0.8 * sat_rate
+    gaps = rng.exponential(1.0 / rate, size=n_requests)
+    lat, wall, st = run_server(gaps)
+
+    # plain per-request FP64 path on the same arrival trace
+    arrivals = np.cumsum(gaps)
+    plain_lat = []
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    t0 = time.perf_counter()
+    for (c, phi, p, h, b), ta in zip(reqs, arrivals):
+        d = t0 + ta - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        M = mechs[c]
+        J = M.eval_jacobian(dev(phi), dev(p))
+        x, info = M.newton_solve(J, dev(h), dev(b), NEWTON_GAMMA, mode=NEWTON_FP64)
+        x.cpu()
+        plain_lat.append(time.perf_counter() - (t0 + ta))
+        del J, x, info
+    plain_wall = time.perf_counter() - t0
+    plain_lat = np.array(plain_lat)
+    return {
+        "requests": n_requests, "states": int(total_states),
+        "offered_load": "80% of the measured burst saturation rate",
+        "arrival_rate_req_per_s": rate,
+        "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "states_per_s": total_states / wall, "batches": st["batches"],
+        "plain_fp64_per_request": {"p50_ms": float(np.percentile(plain_lat, 50) * 1e3),
+                                   "p99_ms": float(np.percentile(plain_lat, 99) * 1e3),
+                                   "states_per_s": total_states / plain_wall},
+    }
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--states", type=int, default=None, help="override the batch size")
-    ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=120)
     ap.add_argument("--variant", type=str, default=None, help="Jacobian launch shape TS,NT")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -84,8 +187,9 @@ def main() -> int:
 
     import numpy as np
     import torch
-    from paper_1605_03262_amd import Mechanism
-    from synth import CONFIGS, config_mechanism, config_states
+    from paper_1605_03262_amd import NEWTON_FP64, NEWTON_MIXED, Mechanism
+    from synth import (CONFIGS, NEWTON_GAMMA, conditioned_steps, config_mechanism, config_states,
+                       draw_newton_inputs)
 
     c = CONFIGS[CFG]
     mech = config_mechanism(CFG)
@@ -98,7 +202,22 @@ def main() -> int:
     d_phi = torch.from_numpy(phi).cuda()
     d_p = torch.from_numpy(p).cuda()
     jac = torch.empty((N * N, n), dtype=torch.float64, device="cuda")
+    h_cfg, rhs = draw_newton_inputs(3262 + 40, N, n)
+    M.eval_jacobian(d_phi, d_p, out=jac)
+    torch.cuda.synchronize()
+    rows = torch.abs(jac.view(N, N, n)).sum(dim=1).cpu().numpy()
+    h_cond = conditioned_steps(3262 + 41, rows)
+    d_h = torch.from_numpy(h_cond).cuda()
+    d_hcfg = torch.from_numpy(h_cfg).cuda()
+    d_rhs = torch.from_numpy(rhs).cuda()
+    ws = torch.empty((max(M.newton_workspace_bytes(n, 0), M.newton_workspace_bytes(n, 1)),),
+                     dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
+    out = {}
+
+    def newton(mode, hh):
+        return M.newton_solve(jac, hh, d_rhs, NEWTON_GAMMA, mode=mode, max_refine=4, rtol=1e-14,
+                              workspace=ws)
 
     def step(ev=None):
         if ev is not None:
@@ -106,6 +225,7 @@ def main() -> int:
         M.eval_jacobian(d_phi, d_p, out=jac)
         if ev is not None:
             ev[1].record(stream)
+        newton(NEWTON_MIXED, d_h)
 
     for _ in range(args.warmup):
         step()
@@ -118,29 +238,50 @@ def main() -> int:
         step(evs[k])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    jac_ms = [a.elapsed_time(b) for a, b in evs]
-    jac_avg_ms = float(np.mean(jac_ms))
+    jac_ms = np.array([a.elapsed_time(b) for a, b in evs])
+    jac_avg_ms = float(jac_ms.mean())
     ms_per_step = elapsed * 1e3 / args.steps
     value = n * args.steps / elapsed
 
     bytes_alg = n * (8.0 * N * N + 8.0 * (N + 1))
     achieved = bytes_alg / (jac_avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(bytes_alg)
     ts, nt, lds = M.get_variant(1)
 
-    out = {
+    # Newton alone, both modes, both step-size recipes
+    newton_info = {}
+    for label, hh in (("conditioned_h", d_h), ("configured_h", d_hcfg)):
+        res = {}
+        for mode, name in ((NEWTON_FP64, "fp64_lu"), (NEWTON_MIXED, "fp32_mfma_lu_fp64_refine")):
+            med, mean = time_stream(lambda: newton(mode, hh), 3, torch)
+            _, info = newton(mode, hh)
+            torch.cuda.synchronize()
+            info = info[:n].cpu().numpy()
+            res[name] = {"ms_median": med, "states_per_s": n / (med * 1e-3),
+                         "fp64_fallbacks": int((info == -2).sum()), "singular": int((info == -1).sum())}
+            if mode == NEWTON_MIXED:
+                sw = info[info > 0]
+                res[name]["refine_sweeps_mean"] = float(sw.mean()) if sw.size else None
+        res["mixed_speedup"] = res["fp64_lu"]["ms_median"] / res["fp32_mfma_lu_fp64_refine"]["ms_median"]
+        newton_info[label] = res
+
+    out.update({
         "metric": "Jacobian evals/s (FP64, <=1e-10 rel err vs oracle) + p50/p99 request latency",
         "value": value, "unit": "Jacobian evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{c['name']}: {n} states, dense {N}x{N} FP64 Jacobian",
+        "config": {"workload": f"{c['name']}: {n} states, dense {N}x{N} FP64 Jacobian + "
+                               f"mixed-precision Newton solve per step",
                    "n_species": N, "n_reactions": mech.n_reactions, "n_states": n,
                    "jacobian_variant": {"tile_states": ts, "threads": nt, "lds_bytes": lds}},
+        "jacobian_only": {"ms_per_launch": jac_avg_ms, "evals_per_s": n / (jac_avg_ms * 1e-3)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "tile_kernel (Jacobian)", "avg_launch_ms": jac_avg_ms,
                      "algorithmic_bytes_per_launch": bytes_alg},
-    }
+        "newton": newton_info,
+    })
+    if not args.no_serving:
+        out["serving"] = serving_run(args.serving_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mech, phi, p)
     print(json.dumps(out), flush=True)

@@ -60,11 +60,12 @@ typedef int32_t pyjac_status;
 #define PYJAC_E_UNBALANCED   -7   /* a reaction does not conserve elements */
 #define PYJAC_E_WORKSPACE    -8   /* Newton workspace too small */
 
-/* Load a mechanism from the project's text format (see the design doc of the
- * repository: elements, species with NASA-7 coefficients, reactions of the
+/* Load a mechanism from the project's whitespace-separated token format
+ * ("pyjac-mech 1", then elements with atomic weights, species with
+ * composition, T_mid and 2x7 NASA-7 coefficients, and reactions of the
  * classes of Sec. 2.3: elementary, third-body, Lindemann/Troe/SRI falloff and
  * chemically activated, PLOG, Chebyshev; reverse rates via K_c, explicit
- * Arrhenius or irreversible).  Validates element balance and supported
+ * Arrhenius or irreversible; SI-kmol units, activation as T_a in K).  Validates element balance and supported
  * features, packs device tables on HIP device `hip_device` and returns an
  * owned handle in *out.  Errors: PYJAC_E_IO, _PARSE, _UNSUPPORTED,
  * _UNBALANCED, _NOMEM, _DEVICE; *out is left NULL on error. */
@@ -146,6 +147,47 @@ pyjac_status pyjac_mech_set_variant(pyjac_mech* mech, int32_t which, int32_t til
 /* Current launch shape of a kernel family and its dynamic LDS bytes. */
 pyjac_status pyjac_mech_get_variant(const pyjac_mech* mech, int32_t which, int32_t* tile_states,
                                     int32_t* threads, size_t* lds_bytes);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of Jacobian + Newton requests.
+ * A server owns an HBM arena of hbm_budget_bytes on `device` and n_streams
+ * streams.  Requests (host arrays, element-major with the request's own state
+ * count as leading dimension: phi [N][n], p/h [n], rhs [N][n]; outputs x
+ * [N][n], info [n]) are admitted in arrival order when their device footprint
+ * fits the free arena; admitted requests with the same mechanism, mode and
+ * gamma are packed into one batch of at most max_batch_states states and
+ * evaluated (pyjac_eval_jacobian, then pyjac_newton_factor_solve with
+ * max_refine/rtol) while other batches run on other streams.  A state's
+ * result does not depend on the batch it lands in.  Host arrays must stay
+ * valid until the request has completed (pyjac_serve_wait).
+ * ------------------------------------------------------------------------ */
+typedef struct pyjac_server pyjac_server;
+
+/* Errors: PYJAC_E_INVALID (bad parameters), PYJAC_E_NOMEM (budget cannot be
+ * reserved), PYJAC_E_DEVICE. */
+pyjac_status pyjac_serve_create(int32_t device, size_t hbm_budget_bytes, int64_t max_batch_states,
+                                int32_t n_streams, int32_t max_refine, double rtol,
+                                pyjac_server** out);
+
+/* Queues one request and returns its id at once.  Errors: PYJAC_E_INVALID,
+ * PYJAC_E_NOMEM (footprint larger than the whole budget). */
+pyjac_status pyjac_serve_submit(pyjac_server* server, const pyjac_mech* mech, int64_t n_states,
+                                const double* phi, const double* p, const double* h,
+                                const double* rhs, double gamma, int32_t mode, double* x,
+                                int32_t* info, uint64_t* request_id);
+
+/* Blocks until the request completes (timeout_s < 0: no limit) and returns
+ * its latency (completion - submission) in seconds; the id is then released. */
+pyjac_status pyjac_serve_wait(pyjac_server* server, uint64_t request_id, double timeout_s,
+                              double* latency_s);
+
+/* Counters since creation and the p50/p99 latency of all completed requests. */
+pyjac_status pyjac_serve_stats(pyjac_server* server, int64_t* requests_done, int64_t* states_done,
+                               int64_t* batches_done, double* p50_s, double* p99_s,
+                               size_t* hbm_in_use);
+
+/* Completes every submitted request, then frees streams and arena. */
+pyjac_status pyjac_serve_destroy(pyjac_server* server);
 
 /* Static description of a status code. */
 const char* pyjac_status_string(pyjac_status status);

@@ -29,8 +29,7 @@
 // dR_i/dY_j are formed literally from the printed product-rule expressions
 // (Kronecker deltas included, [X]^(nu-1) formed directly, no division by [X]).
 //
-// Readings where the paper is silent or inconsistent (each is also listed in
-// the design doc):
+// Readings where the paper is silent or inconsistent:
 //   * temperature row: the second statement (Sec. 3.2, Eq. jac_dt and the
 //     J_{1,1} expression before it) is used; it follows from differentiating
 //     Eq. (dTdt).  The first statement in Sec. 3.1 misplaces 1/c_p.

@@ -128,3 +128,59 @@ class Mechanism:
 
     def get_variant(self, which: int):
         return _lib.pyjac_mech_get_variant(self._h, which)
+
+
+class Server:
+    """Continuous-batching server (C++ scheduler in the library): requests are
+    admitted by HBM footprint, packed per mechanism and run concurrently on
+    several streams.  Host arrays passed to submit() must stay alive until
+    wait() returns; they are kept referenced here until then."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 64 << 30,
+                 max_batch_states: int = 16384, n_streams: int = 4, max_refine: int = 4,
+                 rtol: float = 1e-14):
+        self._h = _lib.pyjac_serve_create(device, hbm_budget_bytes, max_batch_states, n_streams,
+                                          max_refine, rtol)
+        self._keep = {}
+
+    def submit(self, mech: "Mechanism", phi, p, h, rhs, gamma: float, mode: int = NEWTON_MIXED):
+        """phi [N, n], p [n], h [n], rhs [N, n] as C-contiguous float64 numpy
+        arrays; returns (request id, x [N, n], info [n]) with x/info filled
+        once wait(id) has returned."""
+        import numpy as np
+        phi, p, h, rhs = (np.ascontiguousarray(a, dtype=np.float64) for a in (phi, p, h, rhs))
+        n = phi.shape[1]
+        x = np.empty((mech.n_species, n))
+        info = np.empty(n, dtype=np.int32)
+        rid = _lib.pyjac_serve_submit(self._h, mech.handle, n, phi.ctypes.data, p.ctypes.data,
+                                      h.ctypes.data, rhs.ctypes.data, float(gamma), mode,
+                                      x.ctypes.data, info.ctypes.data)
+        self._keep[rid] = (phi, p, h, rhs, x, info)
+        return rid, x, info
+
+    def wait(self, request_id: int, timeout_s: float = -1.0) -> float:
+        """Latency of the request in seconds once it has completed.  On a
+        timeout the request stays in flight and its arrays stay referenced."""
+        try:
+            lat = _lib.pyjac_serve_wait(self._h, request_id, timeout_s)
+        except PyjacError as err:
+            if "timed out" not in str(err):
+                self._keep.pop(request_id, None)
+            raise
+        self._keep.pop(request_id, None)
+        return lat
+
+    def stats(self):
+        return _lib.pyjac_serve_stats(self._h)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.pyjac_serve_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "PYJAC_OK", -1: "PYJAC_E_INVALID", -2: "PYJAC_E_PARSE",
 EXPORTED = ("pyjac_mech_load", "pyjac_mech_load_string", "pyjac_mech_info", "pyjac_mech_free",
             "pyjac_eval_rates", "pyjac_eval_jacobian", "pyjac_newton_workspace_bytes",
             "pyjac_newton_factor_solve", "pyjac_mech_set_variant", "pyjac_mech_get_variant",
-            "pyjac_status_string", "pyjac_last_error")
+            "pyjac_status_string", "pyjac_last_error", "pyjac_serve_create", "pyjac_serve_submit",
+            "pyjac_serve_wait", "pyjac_serve_stats", "pyjac_serve_destroy")
 
 
 class PyjacError(RuntimeError):
@@ -67,6 +68,19 @@ def load_library() -> ctypes.CDLL:
     lib.pyjac_mech_get_variant.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                            ctypes.POINTER(sz)]
     lib.pyjac_mech_get_variant.restype = st
+    lib.pyjac_serve_create.argtypes = [i32, sz, i64, i32, i32, ctypes.c_double, ctypes.POINTER(vp)]
+    lib.pyjac_serve_create.restype = st
+    lib.pyjac_serve_submit.argtypes = [vp, vp, i64, vp, vp, vp, vp, ctypes.c_double, i32, vp, vp,
+                                       ctypes.POINTER(ctypes.c_uint64)]
+    lib.pyjac_serve_submit.restype = st
+    lib.pyjac_serve_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+    lib.pyjac_serve_wait.restype = st
+    lib.pyjac_serve_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(sz)]
+    lib.pyjac_serve_stats.restype = st
+    lib.pyjac_serve_destroy.argtypes = [vp]
+    lib.pyjac_serve_destroy.restype = st
     lib.pyjac_status_string.argtypes = [st]
     lib.pyjac_status_string.restype = ctypes.c_char_p
     lib.pyjac_last_error.argtypes = []
@@ -137,3 +151,38 @@ def pyjac_mech_get_variant(mech, which):
     check(load_library().pyjac_mech_get_variant(mech, which, ctypes.byref(ts), ctypes.byref(nt),
                                                 ctypes.byref(lds)), "pyjac_mech_get_variant")
     return ts.value, nt.value, lds.value
+
+
+def pyjac_serve_create(device, hbm_budget_bytes, max_batch_states, n_streams, max_refine, rtol) -> int:
+    h = ctypes.c_void_p()
+    check(load_library().pyjac_serve_create(device, hbm_budget_bytes, max_batch_states, n_streams,
+                                            max_refine, rtol, ctypes.byref(h)), "pyjac_serve_create")
+    return h.value
+
+
+def pyjac_serve_submit(server, mech, n, phi, p, h, rhs, gamma, mode, x, info) -> int:
+    rid = ctypes.c_uint64()
+    check(load_library().pyjac_serve_submit(server, mech, n, phi, p, h, rhs, gamma, mode, x, info,
+                                            ctypes.byref(rid)), "pyjac_serve_submit")
+    return rid.value
+
+
+def pyjac_serve_wait(server, request_id, timeout_s=-1.0) -> float:
+    lat = ctypes.c_double()
+    check(load_library().pyjac_serve_wait(server, request_id, timeout_s, ctypes.byref(lat)),
+          "pyjac_serve_wait")
+    return lat.value
+
+
+def pyjac_serve_stats(server):
+    r, s_, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    p50, p99, use = ctypes.c_double(), ctypes.c_double(), ctypes.c_size_t()
+    check(load_library().pyjac_serve_stats(server, ctypes.byref(r), ctypes.byref(s_), ctypes.byref(b),
+                                           ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(use)),
+          "pyjac_serve_stats")
+    return {"requests": r.value, "states": s_.value, "batches": b.value, "p50_s": p50.value,
+            "p99_s": p99.value, "hbm_in_use": use.value}
+
+
+def pyjac_serve_destroy(server) -> None:
+    check(load_library().pyjac_serve_destroy(server), "pyjac_serve_destroy")

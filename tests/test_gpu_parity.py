@@ -1,6 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Gates (numbers fixed here, derived in the design doc):
+Gates (FP64 throughout; the bars leave ~3 orders of margin over the rounding
+differences of the two evaluation orders):
   * Jacobian: per-state relative Frobenius error E_norm <= 1e-10;
   * R_f, R_r, c_i: elementwise relative error <= 1e-12;
   * wdot, dPhi/dt: |error| <= 1e-12 of the gross (cancellation-free) magnitude.

@@ -1,0 +1,62 @@
+"""Continuous-batching server: every request's result equals the same request
+processed alone through the direct path (bitwise), also when requests of
+several mechanisms and sizes are packed together, under HBM backpressure."""
+import numpy as np
+import pytest
+
+from synth import NEWTON_GAMMA, config_mechanism, draw_newton_inputs, draw_states
+
+pytestmark = pytest.mark.gpu
+
+
+def _request(rng, N, n):
+    seed = int(rng.integers(1 << 30))
+    phi, p = draw_states(seed, N, n, T=(800.0, 2200.0), P_atm=(1.0, 50.0), dirichlet=0.3)
+    h, b = draw_newton_inputs(seed + 1, N, n)
+    return phi, p, h, b
+
+
+def _alone(torch, M, phi, p, h, b, mode, max_refine, rtol):
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    J = M.eval_jacobian(d(phi), d(p))
+    x, info = M.newton_solve(J, d(h), d(b), NEWTON_GAMMA, mode=mode, max_refine=max_refine, rtol=rtol)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), info.cpu().numpy()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_results_same_alone_and_in_the_mix(mode):
+    import torch
+    from paper_1605_03262_amd import Mechanism, Server
+    mechs = [Mechanism(text=config_mechanism(c).to_text()) for c in (0, 1, 2)]
+    rng = np.random.default_rng(11 + mode)
+    reqs = []
+    for q in range(14):
+        M = mechs[q % 3]
+        n = int(rng.integers(1, 300))
+        reqs.append((M,) + _request(rng, M.n_species, n))
+    # budget that cannot hold everything at once: forces backpressure
+    srv = Server(hbm_budget_bytes=256 << 20, max_batch_states=512, n_streams=3, max_refine=4,
+                 rtol=1e-14)
+    ids = [srv.submit(M, phi, p, h, b, NEWTON_GAMMA, mode=mode) for (M, phi, p, h, b) in reqs]
+    lat = [srv.wait(rid) for rid, _, _ in ids]
+    st = srv.stats()
+    srv.close()
+    assert st["requests"] == len(reqs) and st["batches"] <= len(reqs)
+    assert all(v > 0 for v in lat)
+    for (M, phi, p, h, b), (rid, x, info) in zip(reqs, ids):
+        xa, ia = _alone(torch, M, phi, p, h, b, mode, 4, 1e-14)
+        assert np.array_equal(info, ia)
+        ok = np.isfinite(xa)
+        assert np.array_equal(x[ok], xa[ok])
+
+
+def test_oversized_request_is_rejected():
+    from paper_1605_03262_amd import Mechanism, PyjacError, Server
+    M = Mechanism(text=config_mechanism(1).to_text())
+    srv = Server(hbm_budget_bytes=8 << 20, max_batch_states=4096, n_streams=1)
+    rng = np.random.default_rng(3)
+    phi, p, h, b = _request(rng, M.n_species, 4000)
+    with pytest.raises(PyjacError):
+        srv.submit(M, phi, p, h, b, NEWTON_GAMMA)
+    srv.close()
