@@ -144,6 +144,24 @@ pyjac_status pyjac_newton_factor_solve(const pyjac_mech* mech, int64_t n_states,
 pyjac_status pyjac_mech_set_variant(pyjac_mech* mech, int32_t which, int32_t tile_states,
                                     int32_t threads);
 
+/* Autotuner: times every compiled launch shape of one kernel family
+ * (which = 0: rates kernel writing the RHS only, 1: Jacobian kernel) that fits
+ * the device and the mechanism, on the caller's own batch (n_states states of
+ * phi[N][ld], p[ld], output written to out: [N][ld] doubles for which = 0,
+ * [N*N][ld] for which = 1), `reps` timed launches each after one warm-up,
+ * and keeps the fastest median for this handle.  Every launch is ordered on
+ * `stream` and the call returns after the last one has finished.  Optional
+ * report: up to max_entries (tile_states, threads) pairs in shapes[2*e],
+ * their median milliseconds in ms[e], and the count in *n_entries.  Since
+ * results per state do not depend on the shape, tuning never changes
+ * answers.  Not thread-safe against concurrent calls on the same handle.
+ * Errors: as pyjac_eval_jacobian / pyjac_eval_rates, PYJAC_E_INVALID for
+ * reps < 1 or n_states < 1, PYJAC_E_DEVICE if timing fails. */
+pyjac_status pyjac_mech_autotune(pyjac_mech* mech, int32_t which, int64_t n_states, int64_t ld,
+                                 const double* phi, const double* p, double* out, int32_t reps,
+                                 int32_t* shapes, float* ms, int32_t max_entries,
+                                 int32_t* n_entries, void* stream);
+
 /* Current launch shape of a kernel family and its dynamic LDS bytes. */
 pyjac_status pyjac_mech_get_variant(const pyjac_mech* mech, int32_t which, int32_t* tile_states,
                                     int32_t* threads, size_t* lds_bytes);

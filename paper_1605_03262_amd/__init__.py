@@ -126,6 +126,20 @@ class Mechanism:
     def set_variant(self, which: int, tile_states: int, threads: int) -> None:
         _lib.pyjac_mech_set_variant(self._h, which, tile_states, threads)
 
+    def autotune(self, which: int, phi, p, out=None, reps: int = 3):
+        """Time every launch shape of kernel family `which` (0 rates, 1
+        Jacobian) on this batch and keep the fastest; returns
+        [((tile_states, threads), median ms), ...]."""
+        torch = _torch()
+        n, ld = self._check_in(phi, p)
+        rows = self.n_species * (self.n_species if which == 1 else 1)
+        if out is None:
+            out = torch.empty((rows, ld), dtype=torch.float64, device=phi.device)
+        elif out.shape[0] != rows or out.stride(0) != ld or out.stride(1) != 1:
+            raise ValueError(f"out must be [{rows}, ld] with the same ld as phi")
+        return _lib.pyjac_mech_autotune(self._h, which, n, ld, phi.data_ptr(), p.data_ptr(),
+                                        out.data_ptr(), reps, self._stream())
+
     def get_variant(self, which: int):
         return _lib.pyjac_mech_get_variant(self._h, which)
 

@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "PYJAC_OK", -1: "PYJAC_E_INVALID", -2: "PYJAC_E_PARSE",
 EXPORTED = ("pyjac_mech_load", "pyjac_mech_load_string", "pyjac_mech_info", "pyjac_mech_free",
             "pyjac_eval_rates", "pyjac_eval_jacobian", "pyjac_newton_workspace_bytes",
             "pyjac_newton_factor_solve", "pyjac_mech_set_variant", "pyjac_mech_get_variant",
+            "pyjac_mech_autotune",
             "pyjac_status_string", "pyjac_last_error", "pyjac_serve_create", "pyjac_serve_submit",
             "pyjac_serve_wait", "pyjac_serve_stats", "pyjac_serve_destroy")
 
@@ -68,6 +69,9 @@ def load_library() -> ctypes.CDLL:
     lib.pyjac_mech_get_variant.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                            ctypes.POINTER(sz)]
     lib.pyjac_mech_get_variant.restype = st
+    lib.pyjac_mech_autotune.argtypes = [vp, i32, i64, i64, vp, vp, vp, i32, ctypes.POINTER(i32),
+                                        ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32), vp]
+    lib.pyjac_mech_autotune.restype = st
     lib.pyjac_serve_create.argtypes = [i32, sz, i64, i32, i32, ctypes.c_double, ctypes.POINTER(vp)]
     lib.pyjac_serve_create.restype = st
     lib.pyjac_serve_submit.argtypes = [vp, vp, i64, vp, vp, vp, vp, ctypes.c_double, i32, vp, vp,
@@ -151,6 +155,16 @@ def pyjac_mech_get_variant(mech, which):
     check(load_library().pyjac_mech_get_variant(mech, which, ctypes.byref(ts), ctypes.byref(nt),
                                                 ctypes.byref(lds)), "pyjac_mech_get_variant")
     return ts.value, nt.value, lds.value
+
+
+def pyjac_mech_autotune(mech, which, n, ld, phi, p, out, reps, stream, max_entries=16):
+    shapes = (ctypes.c_int32 * (2 * max_entries))()
+    ms = (ctypes.c_float * max_entries)()
+    cnt = ctypes.c_int32()
+    check(load_library().pyjac_mech_autotune(mech, which, n, ld, phi, p, out, reps, shapes, ms,
+                                             max_entries, ctypes.byref(cnt), stream),
+          "pyjac_mech_autotune")
+    return [((shapes[2 * e], shapes[2 * e + 1]), ms[e]) for e in range(cnt.value)]
 
 
 def pyjac_serve_create(device, hbm_budget_bytes, max_batch_states, n_streams, max_refine, rtol) -> int:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <fstream>
 #include <mutex>
@@ -287,6 +288,80 @@ pyjac_status pyjac_mech_set_variant(pyjac_mech* m, int32_t which, int32_t ts, in
   pyjac_status rc = ensure_var(m, v, jac);
   if (rc != PYJAC_OK) return rc;
   (jac ? m->jac_var : m->rates_var) = v;
+  return PYJAC_OK;
+}
+
+pyjac_status pyjac_mech_autotune(pyjac_mech* m, int32_t which, int64_t n, int64_t ld, const double* phi,
+                                 const double* p, double* out, int32_t reps, int32_t* shapes, float* ms,
+                                 int32_t max_entries, int32_t* n_entries, void* stream) {
+  if (!m || (which != 0 && which != 1)) return fail(PYJAC_E_INVALID, "bad handle or kernel id");
+  if (reps < 1 || n < 1) return fail(PYJAC_E_INVALID, "reps and n_states must be positive");
+  pyjac_status rc = check_common(m, n, ld, phi, p);
+  if (rc != PYJAC_OK) return rc;
+  if (!out || misaligned(out)) return fail(PYJAC_E_INVALID, "out is NULL or not 8-byte aligned");
+  if (n_entries) *n_entries = 0;
+  const bool jac = which == 1;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  static const int shapes_all[][2] = {{16, 1024}, {16, 512}, {32, 1024}, {64, 1024}, {8, 512},
+                                      {8, 1024},  {4, 512},  {4, 1024},  {2, 512},   {2, 1024}};
+  int prev = 0;
+  hipGetDevice(&prev);
+  hipSetDevice(m->device);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    hipSetDevice(prev);
+    return fail(PYJAC_E_DEVICE, "hipEventCreate failed");
+  }
+  Variant best{0, 0};
+  float best_ms = 0.0f;
+  int count = 0;
+  rc = PYJAC_OK;
+  for (auto& q : shapes_all) {
+    const Variant v{q[0], q[1]};
+    if (kpt_of(m->host.N, v.ts, v.nt) > 8) continue;
+    const size_t lds = tile_lds_bytes(m->host.N, m->host.NR, m->host.NG, v.ts, v.nt, jac);
+    if (lds > m->max_lds) continue;
+    if ((rc = ensure_var(m, v, jac)) != PYJAC_OK) break;
+    const MechDev md = launch_view(m, v, jac);
+    auto launch = [&]() {
+      return jac ? launch_tile(true, v.ts, v.nt, md, n, ld, phi, p, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, out, lds, st)
+                 : launch_tile(false, v.ts, v.nt, md, n, ld, phi, p, nullptr, nullptr, nullptr, nullptr,
+                               out, nullptr, lds, st);
+    };
+    std::vector<float> t;
+    hipError_t err = launch();
+    for (int r = 0; r < reps && err == hipSuccess; ++r) {
+      hipEventRecord(e0, st);
+      err = launch();
+      hipEventRecord(e1, st);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float x = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&x, e0, e1);
+      t.push_back(x);
+    }
+    if (err != hipSuccess) {
+      rc = fail(PYJAC_E_DEVICE, std::string("autotune launch failed: ") + hipGetErrorString(err));
+      break;
+    }
+    std::sort(t.begin(), t.end());
+    const float med = t[t.size() / 2];
+    if (shapes && ms && count < max_entries) {
+      shapes[2 * count] = v.ts;
+      shapes[2 * count + 1] = v.nt;
+      ms[count] = med;
+    }
+    ++count;
+    if (!best.ts || med < best_ms) { best = v; best_ms = med; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipSetDevice(prev);
+  if (rc != PYJAC_OK) return rc;
+  if (!best.ts) return fail(PYJAC_E_UNSUPPORTED, "no launch shape fits");
+  (jac ? m->jac_var : m->rates_var) = best;
+  if (n_entries) *n_entries = count < max_entries ? count : max_entries;
   return PYJAC_OK;
 }
 

@@ -191,7 +191,19 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
     else {
       E = M;
       if (coll == C_EFF)
-        for (int e = R.aux0; e < R.aux1; ++e) E += md.eff_am1[e] * Xs[md.eff_sp[e] * TS];
+        // four entries per step, loads issued together (the lists carry slack)
+        for (int e0 = R.aux0; e0 < R.aux1; e0 += 4) {
+          int sp[4];
+          double am[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            sp[u] = md.eff_sp[e0 + u];
+            am[u] = md.eff_am1[e0 + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (e0 + u < R.aux1) E += am[u] * Xs[sp[u] * TS];
+        }
     }
     if (kind == K_THD) {
       c = E;
@@ -393,6 +405,16 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
   for (int q = 0; q < KPT; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.0;
   for (int c0 = 0, ch = 0; c0 < NR; c0 += Gr, ++ch) {
     const int i = c0 + g;
+    // this chunk's gather bounds and first list entries, fetched before the
+    // reaction evaluation so that their latency overlaps it
+    const int* bnd = md.spg_chunk + (size_t)ch * N;
+    int gb0[KPT], gb1[KPT];
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int k = min(g + q * Gr, N - 1);
+      gb0[q] = bnd[k];
+      gb1[q] = bnd[N + k];
+    }
     if (i < NR) {
       RxnRec Rr;
       {   // hot half of the record: 8 independent 16-byte loads
@@ -421,13 +443,12 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
     __syncthreads();
     // species gathers over this chunk: list entries [bnd[ch][k], bnd[ch+1][k]),
     // fetched four at a time so their loads overlap
-    const int* bnd = md.spg_chunk + (size_t)ch * N;
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
       const int k = g + q * Gr;
       if (k < N) {
-        const int e1 = bnd[N + k];
-        for (int e = bnd[k]; e < e1; e += 4) {
+        const int e1 = gb1[q];
+        for (int e = gb0[q]; e < e1; e += 4) {
           int ent[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) ent[u] = md.spg_ent[e + u];
@@ -514,24 +535,34 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
     double TR = 0.0;
     double2 ab = WAB[0];
     double val = ab.x * vj + ab.y;
+    double hk = H[0];
+    double2 abn = WAB[(N > 1 ? 1 : 0) * TS];
     int k = 0;
-    for (int b = 0; b < cnt; b += kColBatch) {
-      ColRec r[kColBatch];
+    ColRec r[kColBatch];
 #pragma unroll
-      for (int u = 0; u < kColBatch; ++u) r[u] = rec[b + u];
+    for (int u = 0; u < kColBatch; ++u) r[u] = rec[u];
+    for (int b = 0; b < cnt; b += kColBatch) {
+      // the stream carries one batch of slack, so the next batch is always readable
+      ColRec nx[kColBatch];
+#pragma unroll
+      for (int u = 0; u < kColBatch; ++u) nx[u] = rec[b + kColBatch + u];
 #pragma unroll
       for (int u = 0; u < kColBatch; ++u) {
         const int x = r[u].x;
         val += r[u].coef * P[r[u].src * TS] * Xb[(x & 0x7FFF) * TS] * Xb[((x >> 15) & 0x7FFF) * TS];
         if (x & kColMark) {
           if (k < N - 1 && live) *outp = val;
-          TR += H[k * TS] * val;
+          TR += hk * val;
           outp += rstride;
           ++k;
-          ab = WAB[(k < N ? k : N - 1) * TS];
-          val = ab.x * vj + ab.y;
+          val = abn.x * vj + abn.y;
+          const int kn = k + 1 < N ? k + 1 : N - 1;
+          hk = H[min(k, N - 1) * TS];
+          abn = WAB[kn * TS];
         }
       }
+#pragma unroll
+      for (int u = 0; u < kColBatch; ++u) r[u] = nx[u];
     }
     const double* aj = nasa_coeffs(md, j, T);
     const double cpj = (aj[0] + T * (aj[1] + T * (aj[2] + T * (aj[3] + aj[4] * T)))) * kR * md.invW[j];

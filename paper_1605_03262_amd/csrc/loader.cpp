@@ -394,7 +394,8 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
     P.NG = ng;
     if (P.cheb.empty()) P.cheb.push_back(0.0);
     if (P.plog.empty()) P.plog.push_back(0.0);
-    if (P.eff_sp.empty()) { P.eff_sp.push_back(0); P.eff_am1.push_back(0.0); }
+    // slack for the four-at-a-time efficiency loads
+    for (int u = 0; u < 4; ++u) { P.eff_sp.push_back(0); P.eff_am1.push_back(0.0); }
     // ---- per-species reaction lists (sorted slots ascending), all N species
     std::vector<std::vector<std::pair<int, double>>> lists(N);
     for (int slot = 0; slot < NR; ++slot) {
@@ -476,6 +477,8 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
         while (P.colrec.size() % kColBatch) P.colrec.push_back(ColRec{0.0, -1, N | (N << 15)});
       }
       P.col_start.push_back((int)P.colrec.size());
+      // one batch of slack: the kernel reads the batch after a column's last
+      for (int u = 0; u < kColBatch; ++u) P.colrec.push_back(ColRec{0.0, -1, N | (N << 15)});
     }
     return PYJAC_OK;
   } catch (const LoadError& e) {

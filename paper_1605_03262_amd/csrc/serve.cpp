@@ -110,6 +110,7 @@ struct Batch {
   size_t off = 0, bytes = 0;
   int stream = 0;
   hipEvent_t done_ev = nullptr;
+  bool launched = false;   // set under the lock once done_ev has been recorded
 };
 
 size_t request_bytes(int N, int64_t n, int mode) {
@@ -257,13 +258,18 @@ void scheduler_loop(pyjac_server* S) {
     S->inflight.push_back(std::move(B));
     lk.unlock();
     pyjac_status rc = launch_batch(S, *raw);
+    if (rc != PYJAC_OK) {
+      hipStreamSynchronize(S->streams[raw->stream]);
+      hipEventRecord(raw->done_ev, S->streams[raw->stream]);
+    }
     lk.lock();
     if (rc != PYJAC_OK) {
       S->error = pyjac_last_error();
       for (auto& r : raw->reqs) r->status = rc;
-      hipStreamSynchronize(S->streams[raw->stream]);
-      hipEventRecord(raw->done_ev, S->streams[raw->stream]);
     }
+    // Only now may the completion thread look at the batch: an event that was
+    // never recorded reads as complete.
+    raw->launched = true;
     S->cv_done.notify_all();
   }
 }
@@ -277,19 +283,26 @@ void reaper_loop(pyjac_server* S) {
       S->cv_done.wait_for(lk, std::chrono::milliseconds(5));
       continue;
     }
-    // completion order is by stream; check every in-flight batch
+    // Snapshot the launched batches under the lock and query their events
+    // without it.  Only this thread erases from `inflight`, so the pointers
+    // stay valid while the scheduler appends new batches.
+    std::vector<Batch*> snap;
+    for (auto& b : S->inflight)
+      if (b->launched) snap.push_back(b.get());
+    std::vector<hipError_t> st(snap.size());
+    lk.unlock();
+    for (size_t q = 0; q < snap.size(); ++q) st[q] = hipEventQuery(snap[q]->done_ev);
+    lk.lock();
     bool any = false;
-    for (auto it = S->inflight.begin(); it != S->inflight.end();) {
-      Batch* B = it->get();
-      lk.unlock();
-      hipError_t q = hipEventQuery(B->done_ev);
-      lk.lock();
-      if (q == hipErrorNotReady) { ++it; continue; }
+    for (size_t q = 0; q < snap.size(); ++q) {
+      if (st[q] == hipErrorNotReady) continue;
+      Batch* B = snap[q];
+      const hipError_t qs = st[q];
       const auto now = Clock::now();
       for (auto& r : B->reqs) {
         r->t_done = now;
         r->done = true;
-        if (q != hipSuccess && r->status == PYJAC_OK) r->status = PYJAC_E_DEVICE;
+        if (qs != hipSuccess && r->status == PYJAC_OK) r->status = PYJAC_E_DEVICE;
         S->latencies.push_back(std::chrono::duration<double>(r->t_done - r->t_submit).count());
         S->requests_done += 1;
       }
@@ -298,7 +311,8 @@ void reaper_loop(pyjac_server* S) {
       S->arena.give(B->off, B->bytes);
       S->stream_busy[B->stream] = 0;
       hipEventDestroy(B->done_ev);
-      it = S->inflight.erase(it);
+      for (auto it = S->inflight.begin(); it != S->inflight.end(); ++it)
+        if (it->get() == B) { S->inflight.erase(it); break; }
       any = true;
     }
     if (any) {

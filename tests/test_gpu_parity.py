@@ -213,6 +213,27 @@ def test_launch_shape_does_not_change_results(torch):
     assert tried >= 2
 
 
+def test_autotune_keeps_fastest_and_results(torch):
+    """The autotuner times every shape that fits, keeps the fastest median,
+    and (shape independence) leaves every result bitwise unchanged."""
+    mech = config_mechanism(1)
+    phi, p = config_states(1, 3000)
+    M = gpu_mech(mech)
+    base_j = gpu_jac(torch, M, phi, p)
+    base_r = gpu_rates(torch, M, phi, p)
+    d_phi, d_p = torch.from_numpy(phi).cuda(), torch.from_numpy(p).cuda()
+    for which in (1, 0):
+        rep = M.autotune(which, d_phi, d_p, reps=3)
+        assert len(rep) >= 2
+        best = min(rep, key=lambda e: e[1])[0]
+        ts, nt, _ = M.get_variant(which)
+        assert (ts, nt) == best
+    assert np.array_equal(base_j, gpu_jac(torch, M, phi, p))
+    r = gpu_rates(torch, M, phi, p)
+    for k in r:
+        assert np.array_equal(base_r[k], r[k]), k
+
+
 # ---------------------------------------------------------------- edge cases
 def test_edge_cases(torch):
     from paper_1605_03262_amd import PyjacError
