@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdint>
 #include <string>
+#include <utility>
 
 #include "../../include/pyjac.h"
 #include "tables.hpp"
@@ -238,6 +239,356 @@ __global__ __launch_bounds__(LU_THREADS) void lu_kernel(int N, int64_t n, T* __r
   if (tid == 0 && singular) status[st] = sing_code;
 }
 
+__global__ void zero_int_kernel(int* p) { *p = 0; }
+
+// ---------------------------------------------------------------- small systems
+// N <= 64: one wavefront per state, lane i holding row i of I - h gamma J in
+// registers (NM = 16, 32 or 64 columns, indexed by compile-time constants
+// only; columns N..NM-1 are zero, so every update runs unguarded over the
+// full width).  A block of SW states shares one workgroup only to read the
+// state-fastest Jacobian in coalesced 64-byte runs through LDS; after that
+// every wavefront factors and solves on its own, with no barrier:
+//  * right-looking LU with partial pivoting, rows kept in place (lane i keeps
+//    row i; `stp` records the elimination step at which it became the pivot
+//    row).  The pivot is the active lane with the largest |a_ik| (compared on
+//    the high 32 bits of the FP64/FP32 pattern, which order non-negative
+//    values; ties go to the lowest lane); the pivot row reaches the other
+//    lanes through v_readlane.
+//  * forward and backward substitution in pivot order, in FP64 arithmetic.
+//  * mixed mode: FP32 factor, FP64 rows kept beside it for the residuals;
+//    states that do not converge within max_refine sweeps (or whose FP32
+//    factor is singular) are listed and re-solved by the FP64 kernel.
+constexpr int kSmallMax = 64;  // largest N taken by the register-resident path
+constexpr int SW8 = 8;         // states (wavefronts) per workgroup, FP64 kernel
+// The mixed kernel holds the FP64 rows beside the FP32 factor; at NM = 64 it
+// runs one wavefront per SIMD (4 per workgroup) so that both fit in registers.
+template <int NM> struct MixedShape { static constexpr int SW = NM >= 64 ? 4 : 8; };
+constexpr int SRB = 16;        // Jacobian rows staged per LDS pass
+
+// Compile-time loop: f(std::integral_constant<int, j>) for j in [B, E), so
+// that register arrays are only ever indexed by constants.
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    sfor<B + 1, E>(f);
+  }
+}
+// The same in groups of 8 with a scheduling barrier after each group, so that
+// LDS operands are not all fetched ahead into registers at once.
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor8(F&& f) {
+  if constexpr (B < E) {
+    constexpr int M = (B + 8 < E) ? B + 8 : E;
+    sfor<B, M>(f);
+    __builtin_amdgcn_sched_barrier(0);
+    sfor8<M, E>(f);
+  }
+}
+
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ float lane_bcast(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ unsigned mag_key(double v) {
+  return (unsigned)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7FFFFFFFu;
+}
+__device__ __forceinline__ unsigned mag_key(float v) { return (unsigned)__float_as_int(v) & 0x7FFFFFFFu; }
+__device__ __forceinline__ int first_lane(unsigned long long m) { return (int)__builtin_ctzll(m); }
+
+// One elimination step K of the LU of the wave's rows (see small_lu).  Every
+// step runs unconditionally (no early exit), so the row array stays one set
+// of registers; a zero or non-finite pivot column only raises `bad`.  The
+// pivot row reaches the other lanes element by element through v_readlane
+// (scalar registers), with no memory round trip.
+template <int K, int NM, typename T>
+__device__ __forceinline__ void small_lu_step(T (&a)[NM], int lane, bool& used, int& stp, bool& bad) {
+  const unsigned key = used ? 0u : mag_key(a[K]);
+  const unsigned mk = __ockl_wfred_max_u32(key);
+  const unsigned inf_key = sizeof(T) == 8 ? 0x7FF00000u : 0x7F800000u;
+  bad = bad || mk == 0u || mk >= inf_key;                    // zero column, or inf/NaN pivot
+  const unsigned long long cand = __ballot(!used && key == mk);
+  const int p = first_lane(cand ? cand : 1ull);
+  const T piv = lane_bcast(a[K], p);
+  if (lane == p) {
+    used = true;
+    stp = K;
+  }
+  // Branch-free update: rows already eliminated (the pivot row included) and
+  // padding rows take a zero multiplier, a - 0 * u being exact for the
+  // finite u of a pivot row.
+  const T rp = T(1) / piv;
+  const T l = used ? T(0) : a[K] * rp;
+  a[K] = used ? a[K] : l;
+  sfor<K + 1, NM>([&](auto j) { a[j] -= l * lane_bcast(a[j], p); });
+}
+
+// LU of the wave's NM x NM block in place (multipliers below, U on and above
+// the pivot step).  The block is the N x N matrix bordered by an identity
+// (rows and columns N..NM-1), so the NM - N extra steps leave the N x N
+// factor unchanged; lanes NM..63 hold nothing and never pivot.  Returns false
+// on a zero or non-finite pivot column.
+template <int NM, typename T, int... K>
+__device__ __forceinline__ bool small_lu_seq(T (&a)[NM], int lane, int& stp, std::integer_sequence<int, K...>) {
+  bool used = lane >= NM, bad = false;
+  stp = used ? NM : -1;
+  (small_lu_step<K, NM, T>(a, lane, used, stp, bad), ...);
+  return !bad;
+}
+template <int NM, typename T>
+__device__ __forceinline__ bool small_lu(T (&a)[NM], int lane, int& stp) {
+  return small_lu_seq<NM, T>(a, lane, stp, std::make_integer_sequence<int, NM>{});
+}
+
+template <int K, int NM, typename T>
+__device__ __forceinline__ void small_fwd_step(const T (&a)[NM], int stp, double& b) {
+  const int p = first_lane(__ballot(stp == K));
+  const double yk = lane_bcast(b, p);
+  if (stp > K) b -= (double)a[K] * yk;
+}
+template <int K, int NM, typename T>
+__device__ __forceinline__ void small_bwd_step(const T (&a)[NM], int stp, double& b, double* xv) {
+  const int p = first_lane(__ballot(stp == K));
+  const double xk = lane_bcast(b, p) / (double)lane_bcast(a[K], p);
+  if (stp == K) xv[K] = xk;
+  if (stp < K) b -= (double)a[K] * xk;
+}
+template <int NM, typename T, int... K>
+__device__ __forceinline__ void small_solve_seq(const T (&a)[NM], int stp, double b, double* xv,
+                                                std::integer_sequence<int, K...>) {
+  (small_fwd_step<K, NM, T>(a, stp, b), ...);
+  (small_bwd_step<NM - 1 - K, NM, T>(a, stp, b, xv), ...);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+// Solves with the factor of small_lu: b is the right-hand side entry of the
+// lane's row (zero on the identity border); x_k lands in xv[k] (wave-private
+// LDS, NM entries).
+template <int NM, typename T>
+__device__ __forceinline__ void small_solve(const T (&a)[NM], int stp, double b, double* xv) {
+  small_solve_seq<NM, T>(a, stp, b, xv, std::make_integer_sequence<int, NM>{});
+}
+
+// Rows of A = I - h gamma J for the SW states of a workgroup (or of the SW
+// listed states when `list` is given), staged SRB rows at a time.  Returns
+// the lane's row in a64 (zero beyond N) and whether it is finite.
+template <int NM, int SW>
+__device__ __forceinline__ bool small_load(double (&a64)[NM], int N, int64_t ld, const double* __restrict__ jac,
+                                           const int64_t* sst, double hg, int lane, int wv, double* stage) {
+  sfor<0, NM>([&](auto j) { a64[j] = 0.0; });
+  // Each thread always serves the same state (the stride is a multiple of
+  // SW) and keeps 8 independent loads in flight before its LDS stores.
+  constexpr int UNR = 8, STRIDE = SW * 64;
+  const int64_t myst = sst[threadIdx.x % SW];
+  for (int i0 = 0; i0 < N; i0 += SRB) {
+    const int rows = min(SRB, N - i0);
+    const int cnt = rows * N * SW;
+    const double* jb = jac + (int64_t)i0 * N * ld + (myst >= 0 ? myst : 0);
+    for (int t0 = threadIdx.x; t0 < cnt; t0 += STRIDE * UNR) {
+      double v[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int t = t0 + u * STRIDE;
+        v[u] = (t < cnt && myst >= 0) ? jb[(int64_t)(t / SW) * ld] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int t = t0 + u * STRIDE;
+        if (t < cnt) stage[t] = v[u];
+      }
+    }
+    __syncthreads();
+    if (lane >= i0 && lane < i0 + rows) {
+      // the raw row J_i., at constant offsets; columns j >= N read other
+      // staged values or the slack of SW * NM doubles after the stage
+      // (the allocation is sized for it) and are replaced below
+      const double* src = stage + (size_t)(lane - i0) * N * SW + wv;
+      sfor8<0, NM>([&](auto j) { a64[j] = src[j * SW]; });
+    }
+    __syncthreads();
+  }
+  // a_ij = delta_ij - h gamma J_ij (one rounding) inside the N x N block,
+  // identity on the border (lanes N..NM-1 start with zero rows)
+  sfor<0, NM>([&](auto j) {
+    const double d = lane == j ? 1.0 : 0.0;
+    a64[j] = j < N ? fma(-hg, a64[j], d) : d;
+  });
+  bool fin = true;
+  sfor<0, NM>([&](auto j) { fin = fin && isfinite(a64[j]); });
+  return fin;
+}
+
+// FP64 path.  Without a list: states blockIdx.x*SW + w, info = 0 / -1 / -3.
+// With a list (the mixed path's fallback): slots blockIdx.x*SW + w < *count
+// name the states, info = -2 / -1.
+template <int NM, int SW = SW8>
+__global__ __launch_bounds__(SW * 64, 2) void small_fp64_kernel(int N, int64_t n, int64_t ld,
+                                                                const double* __restrict__ jac,
+                                                                const double* __restrict__ h, double gamma,
+                                                                const double* __restrict__ rhs,
+                                                                double* __restrict__ x, int* __restrict__ info,
+                                                                const int* __restrict__ list,
+                                                                const int* __restrict__ count) {
+  // wave-private buffers first, so their offsets fit the LDS instructions'
+  // immediate offset fields; the staging area follows
+  extern __shared__ double slds[];
+  double* xall = slds;                                     // SW * NM
+  double* stage = xall + (size_t)SW * NM;                  // SRB * N * SW, then slack
+  __shared__ int64_t sst[SW];                              // state of each wave, -1 if none
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  if (threadIdx.x < SW) {
+    const int64_t lim = list ? *count : n;
+    const int64_t slot = (int64_t)blockIdx.x * SW + threadIdx.x;
+    sst[threadIdx.x] = slot < lim ? (list ? list[slot] : slot) : -1;
+  }
+  __syncthreads();
+  const int64_t s = sst[wv];
+  const bool live = s >= 0;
+  double* xv = xall + (size_t)wv * NM;
+  if (lane < NM) xv[lane] = 0.0;
+  const double hg = live ? h[s] * gamma : 0.0;
+  double a64[NM];
+  const bool fin = __all(small_load<NM, SW>(a64, N, ld, jac, sst, hg, lane, wv, stage));
+  const double b = (live && lane < N) ? rhs[(int64_t)lane * ld + s] : 0.0;
+  int status = fin ? 0 : -3;
+  bool solved = false;
+  if (live && fin) {
+    int stp;
+    if (small_lu<NM, double>(a64, lane, stp)) {
+      small_solve<NM, double>(a64, stp, b, xv);
+      solved = true;
+      status = __all(lane >= N || isfinite(xv[lane])) ? (list ? -2 : 0) : -1;
+    } else status = -1;
+  }
+  if (live && lane == 0) info[s] = status;
+  if (solved && lane < N) x[(int64_t)lane * ld + s] = xv[lane];
+}
+
+// Mixed path: FP32 factor, FP64 residuals from the FP64 rows, at most
+// max_refine sweeps; status ST_UNSET (not converged) or ST_SING32 (FP32 factor
+// singular) is left in info for the FP64 fallback.
+template <int NM, int SW = MixedShape<NM>::SW>
+__global__ __launch_bounds__(SW * 64, SW / 4) void small_mixed_kernel(int N, int64_t n, int64_t ld,
+                                                                 const double* __restrict__ jac,
+                                                                 const double* __restrict__ h, double gamma,
+                                                                 const double* __restrict__ rhs,
+                                                                 double* __restrict__ x, int* __restrict__ info,
+                                                                 int max_refine, double rtol) {
+  extern __shared__ double slds[];
+  double* xall = slds;                                     // SW * NM
+  double* dall = xall + (size_t)SW * NM;                   // SW * NM
+  double* stage = dall + (size_t)SW * NM;                  // SRB * N * SW
+  __shared__ int64_t sst[SW];                              // state of each wave, -1 if none
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  if (threadIdx.x < SW) {
+    const int64_t slot = (int64_t)blockIdx.x * SW + threadIdx.x;
+    sst[threadIdx.x] = slot < n ? slot : -1;
+  }
+  __syncthreads();
+  const int64_t s = sst[wv];
+  const bool live = s >= 0;
+  double* xv = xall + (size_t)wv * NM;
+  double* dv = dall + (size_t)wv * NM;
+  if (lane < NM) {
+    xv[lane] = 0.0;
+    dv[lane] = 0.0;
+  }
+  const double hg = live ? h[s] * gamma : 0.0;
+  double a64[NM];
+  const bool fin = __all(small_load<NM, SW>(a64, N, ld, jac, sst, hg, lane, wv, stage));
+  const double b = (live && lane < N) ? rhs[(int64_t)lane * ld + s] : 0.0;
+  int status = fin ? ST_UNSET : -3;
+  if (live && fin) {
+    float a32[NM];
+    sfor<0, NM>([&](auto j) { a32[j] = (float)a64[j]; });
+    int stp;
+    if (!small_lu<NM, float>(a32, lane, stp)) {
+      status = ST_SING32;
+    } else {
+      small_solve<NM, float>(a32, stp, b, xv);                     // sweep 0
+      for (int sweep = 1; sweep <= max_refine; ++sweep) {
+        double r = b;                                                 // r = b - A x, FP64
+        sfor8<0, NM>([&](auto j) { r -= a64[j] * xv[j]; });
+        small_solve<NM, float>(a32, stp, r, dv);
+        double dm = 0.0, xm = 0.0;
+        bool xf = true;
+        if (lane < N) {
+          const double xn = xv[lane] + dv[lane];
+          xv[lane] = xn;
+          dm = fabs(dv[lane]);
+          xm = fabs(xn);
+          xf = isfinite(xn);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int o = 32; o > 0; o >>= 1) {
+          dm = fmax(dm, __shfl_xor(dm, o));
+          xm = fmax(xm, __shfl_xor(xm, o));
+        }
+        if (__all(xf) && dm <= rtol * xm) {
+          status = sweep;
+          break;
+        }
+      }
+    }
+  }
+  if (live && lane == 0) info[s] = status;
+  if (live && status > 0 && lane < N) x[(int64_t)lane * ld + s] = xv[lane];
+}
+
+// States whose mixed solve left ST_UNSET or ST_SING32 go to the fallback list.
+__global__ void small_compact_kernel(int64_t n, const int* __restrict__ info, int* __restrict__ list,
+                                     int* __restrict__ count) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  if (info[s] == ST_UNSET || info[s] == ST_SING32) list[atomicAdd(count, 1)] = (int)s;
+}
+
+// up to two SW x NM buffers + the stage + SW x NM slack for the masked
+// reads past the last staged row
+size_t small_lds(int N, int NM, int SW) { return ((size_t)SRB * N * SW + 3 * (size_t)SW * NM) * sizeof(double); }
+
+template <int NM>
+hipError_t launch_small_t(int N, int64_t n, int64_t ld, const double* jac, const double* h, double gamma,
+                          const double* rhs, double* x, int* info, int mode, int max_refine, double rtol,
+                          int* list, int* count, hipStream_t st) {
+  const size_t lds = small_lds(N, NM, SW8);
+  const unsigned grid = (unsigned)((n + SW8 - 1) / SW8);
+  auto k64 = small_fp64_kernel<NM>;
+  hipError_t e = hipFuncSetAttribute((const void*)k64, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (mode == 0) {
+    hipLaunchKernelGGL(k64, dim3(grid), dim3(SW8 * 64), lds, st, N, n, ld, jac, h, gamma, rhs, x, info,
+                       (const int*)nullptr, (const int*)nullptr);
+    return hipGetLastError();
+  }
+  constexpr int SWM = MixedShape<NM>::SW;
+  const size_t ldsm = small_lds(N, NM, SWM);
+  auto km = small_mixed_kernel<NM>;
+  e = hipFuncSetAttribute((const void*)km, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(km, dim3((unsigned)((n + SWM - 1) / SWM)), dim3(SWM * 64), ldsm, st, N, n, ld, jac, h, gamma,
+                     rhs, x, info, max_refine, rtol);
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, count);
+  hipLaunchKernelGGL(small_compact_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
+                     (const int*)info, list, count);
+  hipLaunchKernelGGL(k64, dim3(grid), dim3(SW8 * 64), lds, st, N, n, ld, jac, h, gamma, rhs, x, info,
+                     (const int*)list, (const int*)count);
+  return hipGetLastError();
+}
+
+hipError_t launch_small(int N, int64_t n, int64_t ld, const double* jac, const double* h, double gamma,
+                        const double* rhs, double* x, int* info, int mode, int max_refine, double rtol,
+                        int* list, int* count, hipStream_t st) {
+  if (N <= 16) return launch_small_t<16>(N, n, ld, jac, h, gamma, rhs, x, info, mode, max_refine, rtol, list, count, st);
+  if (N <= 32) return launch_small_t<32>(N, n, ld, jac, h, gamma, rhs, x, info, mode, max_refine, rtol, list, count, st);
+  if (N <= 64) return launch_small_t<64>(N, n, ld, jac, h, gamma, rhs, x, info, mode, max_refine, rtol, list, count, st);
+  return hipErrorInvalidValue;
+}
+
 // ---------------------------------------------------------------- solve
 // One wavefront per (listed) state, 4 states per 256-thread block; waves
 // without work stay in the block and only skip the memory operations, so
@@ -386,9 +737,9 @@ __global__ void finish_kernel(int N, int64_t n, int64_t ld, const int* __restric
   info[s] = st;
 }
 
-__global__ void zero_int_kernel(int* p) { *p = 0; }
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+size_t small_ws_bytes(int64_t n, int mode) { return mode == 1 ? align256((size_t)n * sizeof(int)) + 256 : 0; }
 
 struct WsLayout {
   size_t a32 = 0, a64 = 0, piv = 0, status = 0, fbstatus = 0, xs = 0, rbuf = 0, list = 0, count = 0, total = 0;
@@ -441,6 +792,7 @@ extern "C" {
 
 size_t pyjac_newton_workspace_bytes(const pyjac_mech* m, int64_t n, int32_t mode) {
   if (!m || n < 0 || (mode != 0 && mode != 1)) return 0;
+  if (mech_species(m) <= kSmallMax) return small_ws_bytes(n, mode);
   return ws_layout(mech_species(m), n, mode).total;
 }
 
@@ -462,11 +814,22 @@ pyjac_status pyjac_newton_factor_solve(const pyjac_mech* m, int64_t n, int64_t l
   if (hipGetDevice(&cur) != hipSuccess || cur != mech_device(m))
     return fail(PYJAC_E_INVALID, "current HIP device differs from the mechanism's device");
   const int N = mech_species(m);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (N <= kSmallMax) {     // register-resident path; mixed mode needs only the fallback list
+    const size_t need = small_ws_bytes(n, mode);
+    if (need && (!workspace || workspace_bytes < need))
+      return fail(PYJAC_E_WORKSPACE, "workspace smaller than pyjac_newton_workspace_bytes");
+    int* list = need ? reinterpret_cast<int*>(workspace) : nullptr;
+    int* count = need ? reinterpret_cast<int*>(static_cast<char*>(workspace) + align256((size_t)n * sizeof(int)))
+                      : nullptr;
+    const hipError_t e = launch_small(N, n, ld, jac, h, gamma, rhs, x, info, mode, max_refine, rtol, list, count, st);
+    if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("newton launch failed: ") + hipGetErrorString(e));
+    return PYJAC_OK;
+  }
   const WsLayout L = ws_layout(N, n, mode);
   if (!workspace || workspace_bytes < L.total) return fail(PYJAC_E_WORKSPACE, "workspace smaller than pyjac_newton_workspace_bytes");
   if (lu_lds(N, sizeof(double)) > 163840) return fail(PYJAC_E_UNSUPPORTED, "mechanism too large for the LU kernel");
   char* w = static_cast<char*>(workspace);
-  hipStream_t st = static_cast<hipStream_t>(stream);
   int* status = reinterpret_cast<int*>(w + L.status);
   int* fbs = reinterpret_cast<int*>(w + L.fbstatus);
   int* piv = reinterpret_cast<int*>(w + L.piv);
