@@ -176,13 +176,16 @@ pyjac_status pyjac_mech_get_variant(const pyjac_mech* mech, int32_t which, int32
  * gamma are packed into one batch of at most max_batch_states states and
  * evaluated (pyjac_eval_jacobian, then pyjac_newton_factor_solve with
  * max_refine/rtol) while other batches run on other streams.  A state's
- * result does not depend on the batch it lands in.  Host arrays must stay
- * valid until the request has completed (pyjac_serve_wait).
+ * result does not depend on the batch it lands in.  Inputs are copied into
+ * pinned host staging memory (min(budget / 4, 2 GiB), at least 64 MiB) during
+ * submit, which blocks while that memory is full; outputs are written to the
+ * caller's x / info when the request completes, so those two arrays must stay
+ * valid until pyjac_serve_wait has returned.
  * ------------------------------------------------------------------------ */
 typedef struct pyjac_server pyjac_server;
 
-/* Errors: PYJAC_E_INVALID (bad parameters), PYJAC_E_NOMEM (budget cannot be
- * reserved), PYJAC_E_DEVICE. */
+/* Errors: PYJAC_E_INVALID (bad parameters), PYJAC_E_NOMEM (budget or pinned
+ * staging memory cannot be reserved), PYJAC_E_DEVICE. */
 pyjac_status pyjac_serve_create(int32_t device, size_t hbm_budget_bytes, int64_t max_batch_states,
                                 int32_t n_streams, int32_t max_refine, double rtol,
                                 pyjac_server** out);

@@ -147,8 +147,9 @@ class Mechanism:
 class Server:
     """Continuous-batching server (C++ scheduler in the library): requests are
     admitted by HBM footprint, packed per mechanism and run concurrently on
-    several streams.  Host arrays passed to submit() must stay alive until
-    wait() returns; they are kept referenced here until then."""
+    several streams.  submit() copies the inputs into pinned staging memory;
+    the output arrays it returns are filled when the request completes and
+    are kept referenced here until wait() returns."""
 
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 64 << 30,
                  max_batch_states: int = 16384, n_streams: int = 4, max_refine: int = 4,

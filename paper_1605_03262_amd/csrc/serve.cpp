@@ -41,16 +41,24 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// First-fit sub-allocator over one device allocation (256-byte granules).
+// First-fit sub-allocator over one device allocation or one pinned host
+// allocation (256-byte granules).
 class Arena {
  public:
-  bool init(size_t bytes) {
+  bool init(size_t bytes, bool pinned_host = false) {
     size_ = (bytes + 255) & ~size_t(255);
-    if (hipMalloc(&base_, size_) != hipSuccess) return false;
+    host_ = pinned_host;
+    const hipError_t e = host_ ? hipHostMalloc(&base_, size_, hipHostMallocDefault) : hipMalloc(&base_, size_);
+    if (e != hipSuccess) {
+      base_ = nullptr;
+      return false;
+    }
     free_[0] = size_;
     return true;
   }
-  ~Arena() { if (base_) hipFree(base_); }
+  ~Arena() {
+    if (base_) (host_ ? hipHostFree(base_) : hipFree(base_));
+  }
   // returns offset or SIZE_MAX
   size_t take(size_t bytes) {
     bytes = (bytes + 255) & ~size_t(255);
@@ -82,6 +90,7 @@ class Arena {
 
  private:
   void* base_ = nullptr;
+  bool host_ = false;
   size_t size_ = 0, used_ = 0;
   std::map<size_t, size_t> free_;
 };
@@ -97,6 +106,11 @@ struct Request {
   double* x = nullptr;
   int32_t* info = nullptr;
   size_t bytes = 0;
+  // pinned staging slot: phi [N][n], p [n], h [n], rhs [N][n] in, x [N][n],
+  // info [n] out; the caller's arrays are only touched by submit (inputs)
+  // and by the completion thread (outputs)
+  size_t pin_off = 0, pin_bytes = 0;
+  char* pin = nullptr;
   Clock::time_point t_submit, t_done;
   bool done = false;
   pyjac_status status = PYJAC_OK;
@@ -112,6 +126,23 @@ struct Batch {
   hipEvent_t done_ev = nullptr;
   bool launched = false;   // set under the lock once done_ev has been recorded
 };
+
+struct PinLayout {
+  size_t phi, p, h, rhs, x, info, total;
+};
+PinLayout pin_layout(int N, int64_t n) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  PinLayout L;
+  size_t o = 0;
+  L.phi = o; o += al((size_t)N * n * 8);
+  L.p = o; o += al((size_t)n * 8);
+  L.h = o; o += al((size_t)n * 8);
+  L.rhs = o; o += al((size_t)N * n * 8);
+  L.x = o; o += al((size_t)N * n * 8);
+  L.info = o; o += al((size_t)n * 4);
+  L.total = o;
+  return L;
+}
 
 size_t request_bytes(int N, int64_t n, int mode) {
   (void)mode;
@@ -133,12 +164,13 @@ struct pyjac_server {
   int64_t max_batch = 4096;
   int max_refine = 4;
   double rtol = 1e-14;
-  Arena arena;
+  Arena arena;                 // device memory of admitted batches
+  Arena pinned;                // host staging of submitted requests
   std::vector<hipStream_t> streams;
   std::vector<int> stream_busy;
 
   std::mutex mu;
-  std::condition_variable cv_sched, cv_done;
+  std::condition_variable cv_sched, cv_done, cv_pin;
   std::deque<std::shared_ptr<Request>> pending;
   std::map<uint64_t, std::shared_ptr<Request>> all;
   std::deque<std::unique_ptr<Batch>> inflight;
@@ -178,10 +210,11 @@ pyjac_status launch_batch(pyjac_server* S, Batch& B) {
   int64_t col = 0;
   for (auto& r : B.reqs) {
     const size_t w = (size_t)r->n * 8;
-    if (hipMemcpy2DAsync(phi + col, n * 8, r->phi, w, w, N, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(p + col, r->p, w, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(h + col, r->h, w, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpy2DAsync(rhs + col, n * 8, r->rhs, w, w, N, hipMemcpyHostToDevice, st) != hipSuccess)
+    const PinLayout P = pin_layout(N, r->n);
+    if (hipMemcpy2DAsync(phi + col, n * 8, r->pin + P.phi, w, w, N, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(p + col, r->pin + P.p, w, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(h + col, r->pin + P.h, w, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpy2DAsync(rhs + col, n * 8, r->pin + P.rhs, w, w, N, hipMemcpyHostToDevice, st) != hipSuccess)
       return pyjac::fail(PYJAC_E_DEVICE, "request copy-in failed");
     col += r->n;
   }
@@ -193,8 +226,9 @@ pyjac_status launch_batch(pyjac_server* S, Batch& B) {
   col = 0;
   for (auto& r : B.reqs) {
     const size_t w = (size_t)r->n * 8;
-    if (hipMemcpy2DAsync(r->x, w, x + col, n * 8, w, N, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipMemcpyAsync(r->info, info + col, (size_t)r->n * 4, hipMemcpyDeviceToHost, st) != hipSuccess)
+    const PinLayout P = pin_layout(N, r->n);
+    if (hipMemcpy2DAsync(r->pin + P.x, w, x + col, n * 8, w, N, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(r->pin + P.info, info + col, (size_t)r->n * 4, hipMemcpyDeviceToHost, st) != hipSuccess)
       return pyjac::fail(PYJAC_E_DEVICE, "request copy-out failed");
     col += r->n;
   }
@@ -293,6 +327,19 @@ void reaper_loop(pyjac_server* S) {
     lk.unlock();
     for (size_t q = 0; q < snap.size(); ++q) st[q] = hipEventQuery(snap[q]->done_ev);
     lk.lock();
+    // results of the finished batches go from the pinned slots to the
+    // callers' arrays without the lock (the requests are not done yet, so
+    // nobody else touches those slots)
+    lk.unlock();
+    for (size_t q = 0; q < snap.size(); ++q) {
+      if (st[q] != hipSuccess) continue;
+      for (auto& r : snap[q]->reqs) {
+        const PinLayout P = pin_layout(r->N, r->n);
+        std::memcpy(r->x, r->pin + P.x, (size_t)r->N * r->n * 8);
+        std::memcpy(r->info, r->pin + P.info, (size_t)r->n * 4);
+      }
+    }
+    lk.lock();
     bool any = false;
     for (size_t q = 0; q < snap.size(); ++q) {
       if (st[q] == hipErrorNotReady) continue;
@@ -300,6 +347,8 @@ void reaper_loop(pyjac_server* S) {
       const hipError_t qs = st[q];
       const auto now = Clock::now();
       for (auto& r : B->reqs) {
+        S->pinned.give(r->pin_off, r->pin_bytes);
+        r->pin = nullptr;
         r->t_done = now;
         r->done = true;
         if (qs != hipSuccess && r->status == PYJAC_OK) r->status = PYJAC_E_DEVICE;
@@ -318,6 +367,7 @@ void reaper_loop(pyjac_server* S) {
     if (any) {
       S->cv_sched.notify_all();
       S->cv_done.notify_all();
+      S->cv_pin.notify_all();
     } else {
       lk.unlock();
       std::this_thread::sleep_for(std::chrono::microseconds(50));
@@ -349,6 +399,11 @@ pyjac_status pyjac_serve_create(int32_t device, size_t hbm_budget_bytes, int64_t
   if (!S->arena.init(hbm_budget_bytes)) {
     hipSetDevice(prev);
     return pyjac::fail(PYJAC_E_NOMEM, "cannot reserve the HBM budget");
+  }
+  const size_t pin_bytes = std::max<size_t>(64u << 20, std::min<size_t>(hbm_budget_bytes / 4, size_t(2) << 30));
+  if (!S->pinned.init(pin_bytes, true)) {
+    hipSetDevice(prev);
+    return pyjac::fail(PYJAC_E_NOMEM, "cannot allocate pinned host staging memory");
   }
   for (int i = 0; i < n_streams; ++i) {
     hipStream_t st;
@@ -387,13 +442,33 @@ pyjac_status pyjac_serve_submit(pyjac_server* S, const pyjac_mech* mech, int64_t
   r->bytes = batch_bytes(mech, r->N, n_states, mode);
   if (r->bytes > S->arena.size()) return pyjac::fail(PYJAC_E_NOMEM, "request larger than the server's HBM budget");
   if (n_states > S->max_batch) return pyjac::fail(PYJAC_E_INVALID, "request larger than max_batch_states");
-  std::lock_guard<std::mutex> g(S->mu);
-  if (S->stop) return pyjac::fail(PYJAC_E_INVALID, "server is shutting down");
+  const PinLayout P = pin_layout(r->N, n_states);
+  r->pin_bytes = P.total;
+  if (P.total > S->pinned.size()) return pyjac::fail(PYJAC_E_NOMEM, "request larger than the pinned staging memory");
+  const auto t0 = Clock::now();
+  std::unique_lock<std::mutex> lk(S->mu);
+  // backpressure on the submitting thread while the staging memory is full
+  size_t off = SIZE_MAX;
+  while (!S->stop && (off = S->pinned.take(P.total)) == SIZE_MAX) S->cv_pin.wait(lk);
+  if (S->stop) {
+    if (off != SIZE_MAX) S->pinned.give(off, P.total);
+    return pyjac::fail(PYJAC_E_INVALID, "server is shutting down");
+  }
+  r->pin_off = off;
+  r->pin = S->pinned.ptr(off);
+  lk.unlock();
+  const size_t w = (size_t)n_states * 8;
+  std::memcpy(r->pin + P.phi, phi, (size_t)r->N * w);
+  std::memcpy(r->pin + P.p, p, w);
+  std::memcpy(r->pin + P.h, h, w);
+  std::memcpy(r->pin + P.rhs, rhs, (size_t)r->N * w);
+  lk.lock();
   r->id = S->next_id++;
-  r->t_submit = Clock::now();
+  r->t_submit = t0;
   S->pending.push_back(r);
   S->all[r->id] = r;
   *request_id = r->id;
+  lk.unlock();
   S->cv_sched.notify_all();
   return PYJAC_OK;
 }
@@ -443,6 +518,7 @@ pyjac_status pyjac_serve_destroy(pyjac_server* S) {
   }
   S->cv_sched.notify_all();
   S->cv_done.notify_all();
+  S->cv_pin.notify_all();
   if (S->sched.joinable()) S->sched.join();
   if (S->reaper.joinable()) S->reaper.join();
   int prev = 0;
