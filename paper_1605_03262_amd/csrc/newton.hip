@@ -254,15 +254,12 @@ __global__ void zero_int_kernel(int* p) { *p = 0; }
 //    the high 32 bits of the FP64/FP32 pattern, which order non-negative
 //    values; ties go to the lowest lane); the pivot row reaches the other
 //    lanes through v_readlane.
-//  * forward and backward substitution in pivot order, in FP64 arithmetic.
+//  * forward and backward substitution in pivot order, in the factor's precision.
 //  * mixed mode: FP32 factor, FP64 rows kept beside it for the residuals;
 //    states that do not converge within max_refine sweeps (or whose FP32
 //    factor is singular) are listed and re-solved by the FP64 kernel.
 constexpr int kSmallMax = 64;  // largest N taken by the register-resident path
-constexpr int SW8 = 8;         // states (wavefronts) per workgroup, FP64 kernel
-// The mixed kernel holds the FP64 rows beside the FP32 factor; at NM = 64 it
-// runs one wavefront per SIMD (4 per workgroup) so that both fit in registers.
-template <int NM> struct MixedShape { static constexpr int SW = NM >= 64 ? 4 : 8; };
+constexpr int SW8 = 8;         // states (wavefronts) per workgroup
 constexpr int SRB = 16;        // Jacobian rows staged per LDS pass
 
 // Compile-time loop: f(std::integral_constant<int, j>) for j in [B, E), so
@@ -283,6 +280,15 @@ __device__ __forceinline__ void sfor8(F&& f) {
     sfor<B, M>(f);
     __builtin_amdgcn_sched_barrier(0);
     sfor8<M, E>(f);
+  }
+}
+
+// Marks every entry of a register array as modified (no code emitted).
+template <int J, int NM, typename T>
+__device__ __forceinline__ void opaque_regs(T (&a)[NM]) {
+  if constexpr (J < NM) {
+    __asm__ volatile("" : "+v"(a[J]));
+    opaque_regs<J + 1, NM>(a);
   }
 }
 
@@ -346,31 +352,33 @@ __device__ __forceinline__ bool small_lu(T (&a)[NM], int lane, int& stp) {
 }
 
 template <int K, int NM, typename T>
-__device__ __forceinline__ void small_fwd_step(const T (&a)[NM], int stp, double& b) {
+__device__ __forceinline__ void small_fwd_step(const T (&a)[NM], int stp, T& b) {
   const int p = first_lane(__ballot(stp == K));
-  const double yk = lane_bcast(b, p);
-  if (stp > K) b -= (double)a[K] * yk;
+  const T yk = lane_bcast(b, p);
+  if (stp > K) b -= a[K] * yk;
 }
 template <int K, int NM, typename T>
-__device__ __forceinline__ void small_bwd_step(const T (&a)[NM], int stp, double& b, double* xv) {
+__device__ __forceinline__ void small_bwd_step(const T (&a)[NM], int stp, T& b, double* xv) {
   const int p = first_lane(__ballot(stp == K));
-  const double xk = lane_bcast(b, p) / (double)lane_bcast(a[K], p);
-  if (stp == K) xv[K] = xk;
-  if (stp < K) b -= (double)a[K] * xk;
+  const T xk = lane_bcast(b, p) / lane_bcast(a[K], p);
+  if (stp == K) xv[K] = (double)xk;
+  if (stp < K) b -= a[K] * xk;
 }
 template <int NM, typename T, int... K>
-__device__ __forceinline__ void small_solve_seq(const T (&a)[NM], int stp, double b, double* xv,
+__device__ __forceinline__ void small_solve_seq(const T (&a)[NM], int stp, T b, double* xv,
                                                 std::integer_sequence<int, K...>) {
   (small_fwd_step<K, NM, T>(a, stp, b), ...);
   (small_bwd_step<NM - 1 - K, NM, T>(a, stp, b, xv), ...);
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
-// Solves with the factor of small_lu: b is the right-hand side entry of the
-// lane's row (zero on the identity border); x_k lands in xv[k] (wave-private
-// LDS, NM entries).
+// Solves with the factor of small_lu, in the factor's precision (for the
+// FP32 factor this is the correction solve of the refinement; residual and
+// solution stay FP64): b is the right-hand side entry of the lane's row
+// (zero on the identity border); x_k lands in xv[k] (wave-private LDS, NM
+// entries).
 template <int NM, typename T>
 __device__ __forceinline__ void small_solve(const T (&a)[NM], int stp, double b, double* xv) {
-  small_solve_seq<NM, T>(a, stp, b, xv, std::make_integer_sequence<int, NM>{});
+  small_solve_seq<NM, T>(a, stp, (T)b, xv, std::make_integer_sequence<int, NM>{});
 }
 
 // Rows of A = I - h gamma J for the SW states of a workgroup (or of the SW
@@ -471,8 +479,8 @@ __global__ __launch_bounds__(SW * 64, 2) void small_fp64_kernel(int N, int64_t n
 // Mixed path: FP32 factor, FP64 residuals from the FP64 rows, at most
 // max_refine sweeps; status ST_UNSET (not converged) or ST_SING32 (FP32 factor
 // singular) is left in info for the FP64 fallback.
-template <int NM, int SW = MixedShape<NM>::SW>
-__global__ __launch_bounds__(SW * 64, SW / 4) void small_mixed_kernel(int N, int64_t n, int64_t ld,
+template <int NM, int SW = SW8>
+__global__ __launch_bounds__(SW * 64, 2) void small_mixed_kernel(int N, int64_t n, int64_t ld,
                                                                  const double* __restrict__ jac,
                                                                  const double* __restrict__ h, double gamma,
                                                                  const double* __restrict__ rhs,
@@ -511,6 +519,7 @@ __global__ __launch_bounds__(SW * 64, SW / 4) void small_mixed_kernel(int N, int
     } else {
       small_solve<NM, float>(a32, stp, b, xv);                     // sweep 0
       for (int sweep = 1; sweep <= max_refine; ++sweep) {
+        opaque_regs<0, NM>(a32);
         double r = b;                                                 // r = b - A x, FP64
         sfor8<0, NM>([&](auto j) { r -= a64[j] * xv[j]; });
         small_solve<NM, float>(a32, stp, r, dv);
@@ -565,7 +574,7 @@ hipError_t launch_small_t(int N, int64_t n, int64_t ld, const double* jac, const
                        (const int*)nullptr, (const int*)nullptr);
     return hipGetLastError();
   }
-  constexpr int SWM = MixedShape<NM>::SW;
+  constexpr int SWM = SW8;
   const size_t ldsm = small_lds(N, NM, SWM);
   auto km = small_mixed_kernel<NM>;
   e = hipFuncSetAttribute((const void*)km, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsm);
