@@ -281,7 +281,7 @@ def main() -> int:
 
     import numpy as np
     import torch
-    from paper_1605_03262_amd import NEWTON_FP64, NEWTON_MIXED, Mechanism
+    from paper_1605_03262_amd import NEWTON_FP64, NEWTON_MIXED, Mechanism, _lib
     from synth import (CONFIGS, NEWTON_GAMMA, conditioned_steps, config_mechanism, config_states,
                        draw_newton_inputs)
 
@@ -345,6 +345,19 @@ def main() -> int:
     achieved = bytes_alg / (jac_avg_ms * 1e-3) / 1e9
     ts, nt, lds = M.get_variant(1)
 
+    # the paper's comparison method: forward-difference Jacobian on the same batch
+    fd_out = torch.empty_like(jac)
+    fd_ws = torch.empty((_lib.pyjac_fd_workspace_bytes(M.handle, 16384),), dtype=torch.uint8, device="cuda")
+    fd_run = lambda: M.eval_jacobian_fd(d_phi, d_p, out=fd_out, workspace=fd_ws)  # noqa: E731
+    fd_run()
+    fd_med, _ = time_stream(fd_run, 3, torch)
+    jac_med, _ = time_stream(lambda: M.eval_jacobian(d_phi, d_p, out=jac), 5, torch)
+    fd_info = {"ms_per_launch": fd_med, "evals_per_s": n / (fd_med * 1e-3),
+                          "analytical_ms_per_launch": jac_med,
+                          "fd_over_analytical_time": fd_med / jac_med,
+                          "method": "first-order forward differences of the GPU RHS, chunks of 16384 states"}
+    del fd_out, fd_ws
+
     # Newton alone, both modes, both step-size recipes
     newton_info = {}
     for label, hh in (("conditioned_h", d_h), ("configured_h", d_hcfg)):
@@ -378,6 +391,7 @@ def main() -> int:
                      "kernel": "tile_kernel (Jacobian)", "avg_launch_ms": jac_avg_ms,
                      "algorithmic_bytes_per_launch": bytes_alg},
         "newton": newton_info,
+        "fd_jacobian": fd_info,
     })
     if not args.no_serving:
         out["serving"] = serving_run(args.serving_requests)

@@ -106,6 +106,21 @@ pyjac_status pyjac_eval_rates(const pyjac_mech* mech, int64_t n_states, int64_t 
 pyjac_status pyjac_eval_jacobian(const pyjac_mech* mech, int64_t n_states, int64_t ld,
                                  const double* phi, const double* p, double* jac, void* stream);
 
+/* Finite-difference Jacobian: the first-order forward-difference
+ * approximation the paper measures the analytical Jacobian against (Sec. 5,
+ * finite differences as in CVODE).  Column j of state s is
+ * (f(Phi + d_j e_j) - f(Phi)) / d_j with f the RHS of pyjac_eval_rates and
+ * d_j = (Phi_j + inc_j) - Phi_j, inc_j = 2^-26 max(|Phi_j|, floor_j) (floor
+ * 1 K for T, 1e-10 for mass fractions).  Same layout as pyjac_eval_jacobian.
+ * States are processed in chunks as large as the workspace allows
+ * (pyjac_fd_workspace_bytes(mech, c) holds a chunk of c states); each chunk
+ * evaluates the RHS kernel on c*(N+1) states.  Errors: as
+ * pyjac_eval_jacobian, PYJAC_E_WORKSPACE if not even one state fits. */
+size_t pyjac_fd_workspace_bytes(const pyjac_mech* mech, int64_t chunk_states);
+pyjac_status pyjac_eval_jacobian_fd(const pyjac_mech* mech, int64_t n_states, int64_t ld, const double* phi,
+                                    const double* p, double* jac, void* workspace, size_t workspace_bytes,
+                                    void* stream);
+
 /* Bytes of device workspace pyjac_newton_factor_solve needs for n_states
  * states in `mode` (0 or 1).  Returns 0 for a bad handle or mode. */
 size_t pyjac_newton_workspace_bytes(const pyjac_mech* mech, int64_t n_states, int32_t mode);

@@ -100,6 +100,23 @@ class Mechanism:
                                  self._stream())
         return out
 
+    def eval_jacobian_fd(self, phi, p, out=None, chunk_states: int = 8192, workspace=None):
+        """Forward-difference Jacobian (same layout as eval_jacobian)."""
+        torch = _torch()
+        n, ld = self._check_in(phi, p)
+        N = self.n_species
+        if out is None:
+            out = torch.empty((N * N, ld), dtype=torch.float64, device=phi.device)
+        elif out.shape[0] != N * N or out.stride(0) != ld or out.stride(1) != 1:
+            raise ValueError("out must be [N*N, ld] with the same ld as phi")
+        if workspace is None:
+            need = _lib.pyjac_fd_workspace_bytes(self._h, max(1, min(n, chunk_states)))
+            workspace = torch.empty((need,), dtype=torch.uint8, device=phi.device)
+        wsb = workspace.numel() * workspace.element_size()
+        _lib.pyjac_eval_jacobian_fd(self._h, n, ld, phi.data_ptr(), p.data_ptr(), out.data_ptr(),
+                                    workspace.data_ptr(), wsb, self._stream())
+        return out
+
     def newton_workspace_bytes(self, n_states: int, mode: int) -> int:
         return _lib.pyjac_newton_workspace_bytes(self._h, n_states, mode)
 

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "PYJAC_OK", -1: "PYJAC_E_INVALID", -2: "PYJAC_E_PARSE",
 EXPORTED = ("pyjac_mech_load", "pyjac_mech_load_string", "pyjac_mech_info", "pyjac_mech_free",
             "pyjac_eval_rates", "pyjac_eval_jacobian", "pyjac_newton_workspace_bytes",
             "pyjac_newton_factor_solve", "pyjac_mech_set_variant", "pyjac_mech_get_variant",
-            "pyjac_mech_autotune",
+            "pyjac_mech_autotune", "pyjac_fd_workspace_bytes", "pyjac_eval_jacobian_fd",
             "pyjac_status_string", "pyjac_last_error", "pyjac_serve_create", "pyjac_serve_submit",
             "pyjac_serve_wait", "pyjac_serve_stats", "pyjac_serve_destroy")
 
@@ -69,6 +69,10 @@ def load_library() -> ctypes.CDLL:
     lib.pyjac_mech_get_variant.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                            ctypes.POINTER(sz)]
     lib.pyjac_mech_get_variant.restype = st
+    lib.pyjac_fd_workspace_bytes.argtypes = [vp, i64]
+    lib.pyjac_fd_workspace_bytes.restype = sz
+    lib.pyjac_eval_jacobian_fd.argtypes = [vp, i64, i64, vp, vp, vp, vp, sz, vp]
+    lib.pyjac_eval_jacobian_fd.restype = st
     lib.pyjac_mech_autotune.argtypes = [vp, i32, i64, i64, vp, vp, vp, i32, ctypes.POINTER(i32),
                                         ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32), vp]
     lib.pyjac_mech_autotune.restype = st
@@ -155,6 +159,15 @@ def pyjac_mech_get_variant(mech, which):
     check(load_library().pyjac_mech_get_variant(mech, which, ctypes.byref(ts), ctypes.byref(nt),
                                                 ctypes.byref(lds)), "pyjac_mech_get_variant")
     return ts.value, nt.value, lds.value
+
+
+def pyjac_fd_workspace_bytes(mech, chunk_states) -> int:
+    return int(load_library().pyjac_fd_workspace_bytes(mech, chunk_states))
+
+
+def pyjac_eval_jacobian_fd(mech, n, ld, phi, p, jac, workspace, workspace_bytes, stream) -> None:
+    check(load_library().pyjac_eval_jacobian_fd(mech, n, ld, phi, p, jac, workspace, workspace_bytes, stream),
+          "pyjac_eval_jacobian_fd")
 
 
 def pyjac_mech_autotune(mech, which, n, ld, phi, p, out, reps, stream, max_entries=16):

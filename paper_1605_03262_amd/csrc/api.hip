@@ -30,6 +30,12 @@ pyjac_status fail(pyjac_status code, const std::string& msg) {
 
 struct Variant { int ts = 0, nt = 0; };
 
+size_t fd_bytes_per_state(int N);
+hipError_t fd_perturb(int N, int64_t m, int64_t ld, const double* phi, const double* p, int64_t s0, double* phi2,
+                      double* p2, int64_t ld2, double* inc, hipStream_t st);
+hipError_t fd_diff(int N, int64_t m, const double* f2, int64_t ld2, const double* inc, int64_t s0, double* jac,
+                   int64_t ld, hipStream_t st);
+
 }  // namespace pyjac
 
 struct pyjac_mech {
@@ -264,6 +270,47 @@ pyjac_status pyjac_eval_jacobian(const pyjac_mech* m, int64_t n, int64_t ld, con
   hipError_t e = launch_tile(true, v.ts, v.nt, md, n, ld, phi, p, nullptr, nullptr, nullptr, nullptr,
                              nullptr, jac, lds, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("jacobian launch failed: ") + hipGetErrorString(e));
+  return PYJAC_OK;
+}
+
+size_t pyjac_fd_workspace_bytes(const pyjac_mech* m, int64_t chunk_states) {
+  if (!m || chunk_states < 1) return 0;
+  return (size_t)chunk_states * fd_bytes_per_state(m->host.N) + 1024;
+}
+
+pyjac_status pyjac_eval_jacobian_fd(const pyjac_mech* m, int64_t n, int64_t ld, const double* phi, const double* p,
+                                    double* jac, void* workspace, size_t workspace_bytes, void* stream) {
+  pyjac_status rc = check_common(m, n, ld, phi, p);
+  if (rc != PYJAC_OK) return rc;
+  if (n > 0 && !jac) return fail(PYJAC_E_INVALID, "jac is NULL");
+  if (misaligned(jac) || misaligned(workspace)) return fail(PYJAC_E_INVALID, "pointer not 8-byte aligned");
+  if (n == 0) return PYJAC_OK;
+  const int N = m->host.N;
+  const size_t per = fd_bytes_per_state(N);
+  if (!workspace || workspace_bytes < per + 1024) return fail(PYJAC_E_WORKSPACE, "workspace smaller than one state");
+  const int64_t chunk = std::min<int64_t>(n, (int64_t)((workspace_bytes - 1024) / per));
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const Variant v = m->rates_var;
+  const size_t lds = tile_lds_bytes(N, m->host.NR, m->host.NG, v.ts, v.nt, false);
+  const MechDev md = launch_view(m, v, false);
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  for (int64_t s0 = 0; s0 < n; s0 += chunk) {
+    const int64_t mm = std::min(chunk, n - s0), ld2 = mm * (N + 1);
+    char* w = static_cast<char*>(workspace);
+    double* phi2 = reinterpret_cast<double*>(w);
+    w += al((size_t)N * ld2 * 8);
+    double* f2 = reinterpret_cast<double*>(w);
+    w += al((size_t)N * ld2 * 8);
+    double* p2 = reinterpret_cast<double*>(w);
+    w += al((size_t)ld2 * 8);
+    double* inc = reinterpret_cast<double*>(w);
+    hipError_t e = fd_perturb(N, mm, ld, phi, p, s0, phi2, p2, ld2, inc, st);
+    if (e == hipSuccess)
+      e = launch_tile(false, v.ts, v.nt, md, ld2, ld2, phi2, p2, nullptr, nullptr, nullptr, nullptr, f2, nullptr,
+                      lds, st);
+    if (e == hipSuccess) e = fd_diff(N, mm, f2, ld2, inc, s0, jac, ld, st);
+    if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("finite-difference launch failed: ") + hipGetErrorString(e));
+  }
   return PYJAC_OK;
 }
 
