@@ -41,16 +41,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(shape=None):
     """HBM bytes per launch of the Jacobian kernel from the committed rocprofv3
-    counter summary, valid only while the kernel source is unchanged."""
+    counter summary, valid only while the kernel source is unchanged and for
+    the launch shape that was measured."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         d = json.load(fh)
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash() or shape is None:
         return None
-    return d.get("bytes_per_launch")
+    e = d.get("shapes", {}).get(f"{shape[0]}x{shape[1]}")
+    return None if e is None else e["bytes_per_launch"]
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobian_c1_100k_traffic.json")
@@ -88,6 +90,31 @@ PMC_COMMAND = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 120 rocprofv3 -
                "-o {o} --output-format csv -- python3 $R/bench.py --pmc-pass   (R = repository root)")
 
 
+def jacobian_only(cfg: int, steps: int) -> int:
+    """Autotuned Jacobian kernel alone on one workload (for the other mechanism
+    sizes; the benchmark step itself runs the 53-species workload)."""
+    import torch
+    from paper_1605_03262_amd import Mechanism
+    from synth import CONFIGS, config_mechanism, config_states
+    mech = config_mechanism(cfg)
+    phi, p = config_states(cfg)
+    N, n = mech.n_species, phi.shape[1]
+    M = Mechanism(text=mech.to_text(), device=0)
+    d_phi, d_p = torch.from_numpy(phi).cuda(), torch.from_numpy(p).cuda()
+    jac = torch.empty((N * N, n), dtype=torch.float64, device="cuda")
+    tuned = M.autotune(1, d_phi, d_p, out=jac, reps=3)
+    med, mean = time_stream(lambda: M.eval_jacobian(d_phi, d_p, out=jac), max(3, steps), torch)
+    rmed, _ = time_stream(lambda: M.eval_rates(d_phi, d_p, rop_f=False, rop_r=False, pres_mod=False,
+                                               wdot=False), max(3, steps), torch)
+    by = n * (8.0 * N * N + 8.0 * (N + 1))
+    print(json.dumps({"workload": CONFIGS[cfg]["name"], "n_states": n, "n_species": N,
+                      "jacobian_ms_median": med, "jacobian_evals_per_s": n / (med * 1e-3),
+                      "hbm_frac": by / (med * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "rhs_ms_median": rmed, "rhs_evals_per_s": n / (rmed * 1e-3),
+                      "shape": M.get_variant(1)[:2], "autotune": tuned}), flush=True)
+    return 0
+
+
 def _counter_rows(d: str, counter: str):
     import csv
     import glob
@@ -102,29 +129,37 @@ def _counter_rows(d: str, counter: str):
 
 def write_traffic(fetch_dir: str, write_dir: str) -> int:
     """Turn the FETCH_SIZE and WRITE_SIZE runs of pmc_pass into HBM bytes per
-    Jacobian launch, each scaled by what the counter reads for the plain copy
-    (COPY_BYTES read and written), and store them with a hash of the kernel
-    source so that a later kernel change invalidates them."""
+    Jacobian launch for every launch shape the autotuner ran (mean over its
+    dispatches), each counter scaled by what it reads for the plain copy
+    (COPY_BYTES read and written).  Stored with a hash of the kernel source,
+    so that a later kernel change invalidates them."""
+    import re
     from synth import CONFIGS
     out = {"kernel_source_hash": kernel_source_hash(), "workload": CONFIGS[CFG]["name"],
-           "copy_bytes": COPY_BYTES}
-    total = 0.0
+           "copy_bytes": COPY_BYTES, "unit": "bytes per launch of 100,000 states", "shapes": {},
+           "commands": [PMC_COMMAND.format(c="FETCH_SIZE", d=os.path.basename(os.path.normpath(fetch_dir)), o="f"),
+                        PMC_COMMAND.format(c="WRITE_SIZE", d=os.path.basename(os.path.normpath(write_dir)), o="w")]}
+    scale = {}
+    per = {}
     for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = _counter_rows(d, name)
-        tiles = [(k, v) for k, v in rows if "tile_kernel" in k]
         cpy = [v for k, v in rows if "copy" in k.lower()]
-        if len(tiles) < 4 or not cpy:
-            print(f"{name}: missing rows in {d}", file=sys.stderr)
+        if not cpy:
+            print(f"{name}: no copy-kernel row in {d}", file=sys.stderr)
             return 1
-        jac = [v for _, v in tiles[-3:]]           # the timed launches come last
-        kib = sum(jac) / len(jac)
-        factor = (COPY_BYTES / 1024.0) / cpy[-1]
-        out[name] = {"kernel": tiles[-1][0].split("(")[0], "kib_per_launch_raw": kib,
-                     "copy_kib_raw": cpy[-1], "scale": factor, "bytes_per_launch": kib * 1024.0 * factor,
-                     "command": PMC_COMMAND.format(c=name, d=os.path.basename(os.path.normpath(d)),
-                                                   o=name[0].lower())}
-        total += kib * 1024.0 * factor
-    out["bytes_per_launch"] = total
+        scale[name] = (COPY_BYTES / 1024.0) / cpy[-1]
+        for k, v in rows:
+            m = re.search(r"tile_kernel<(\d+), (\d+), \d+, true>", k)
+            if m:
+                per.setdefault(f"{m.group(1)}x{m.group(2)}", {}).setdefault(name, []).append(v)
+    for shape, d in per.items():
+        if len(d) < 2:
+            continue
+        e = {c: sum(v) / len(v) * 1024.0 * scale[c] for c, v in d.items()}
+        e["bytes_per_launch"] = e["FETCH_SIZE"] + e["WRITE_SIZE"]
+        e["dispatches"] = len(d["FETCH_SIZE"])
+        out["shapes"][shape] = e
+    out["scale"] = scale
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out), flush=True)
@@ -264,6 +299,8 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=120)
     ap.add_argument("--variant", type=str, default=None, help="Jacobian launch shape TS,NT")
+    ap.add_argument("--jacobian-only-config", type=int, default=None, metavar="ID",
+                    help="only time the Jacobian kernel on workload ID (0-3) and print its roofline line")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="only run the program that the counter runs profile")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -273,6 +310,8 @@ def main() -> int:
         return write_traffic(*args.write_traffic)
     if args.pmc_pass:
         return pmc_pass()
+    if args.jacobian_only_config is not None:
+        return jacobian_only(args.jacobian_only_config, args.steps)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); states are "
               "independent, so several GPUs would each run this same single-GPU path on their "
@@ -387,7 +426,7 @@ def main() -> int:
                    "autotune_ms": tuned},
         "jacobian_only": {"ms_per_launch": jac_avg_ms, "evals_per_s": n / (jac_avg_ms * 1e-3)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic((ts, nt)),
                      "kernel": "tile_kernel (Jacobian)", "avg_launch_ms": jac_avg_ms,
                      "algorithmic_bytes_per_launch": bytes_alg},
         "newton": newton_info,

@@ -164,7 +164,8 @@ pyjac_status pyjac_mech_set_variant(pyjac_mech* mech, int32_t which, int32_t til
  * the device and the mechanism, on the caller's own batch (n_states states of
  * phi[N][ld], p[ld], output written to out: [N][ld] doubles for which = 0,
  * [N*N][ld] for which = 1), `reps` timed launches each after one warm-up,
- * and keeps the fastest median for this handle.  Every launch is ordered on
+ * and keeps the fastest median for this handle (a shape later in the
+ * preference order must be at least 2 % faster to win).  Every launch is ordered on
  * `stream` and the call returns after the last one has finished.  Optional
  * report: up to max_entries (tile_states, threads) pairs in shapes[2*e],
  * their median milliseconds in ms[e], and the count in *n_entries.  Since

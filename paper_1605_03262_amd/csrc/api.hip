@@ -400,7 +400,9 @@ pyjac_status pyjac_mech_autotune(pyjac_mech* m, int32_t which, int64_t n, int64_
       ms[count] = med;
     }
     ++count;
-    if (!best.ts || med < best_ms) { best = v; best_ms = med; }
+    // a later shape must be clearly faster (2 %) to replace an earlier,
+    // preferred one, so that timing noise does not flip the choice
+    if (!best.ts || med < 0.98f * best_ms) { best = v; best_ms = med; }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);

@@ -308,6 +308,17 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
   }
 }
 
+// Workgroups are dispatched round-robin over the eight XCDs (each with its
+// own L2).  This permutation hands every XCD a contiguous range of tiles, so
+// neighbouring tiles, whose short per-element runs of the Jacobian share
+// cache lines, are written through the same L2.
+__device__ inline unsigned xcd_tile() {
+  constexpr unsigned kXcd = 8;
+  const unsigned b = blockIdx.x, G = gridDim.x;
+  const unsigned q = G / kXcd, r = G % kXcd, x = b % kXcd, i = b / kXcd;
+  return x * q + (x < r ? x : r) + i;
+}
+
 template <int TS, int NT, int KPT, bool JAC>
 __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev md, int64_t n, int64_t ld,
                                                   const double* __restrict__ phi,
@@ -319,7 +330,7 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
   extern __shared__ double lds[];
   const int N = md.N, NR = md.NR, NG = md.NG;
   const int tid = threadIdx.x, s = tid % TS, g = tid / TS;
-  const int64_t sg = (int64_t)blockIdx.x * TS + s;
+  const int64_t sg = (int64_t)xcd_tile() * TS + s;
   const bool live = sg < n;
   const int64_t sl = live ? sg : n - 1;
   const TileLayout L(N, NR, NG, Gr, JAC);

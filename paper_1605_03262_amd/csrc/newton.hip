@@ -283,6 +283,16 @@ __device__ __forceinline__ void sfor8(F&& f) {
   }
 }
 
+// Workgroups are dispatched round-robin over the eight XCDs; this permutation
+// gives every XCD a contiguous range of blocks, so neighbouring blocks, whose
+// 64-byte runs of the Jacobian share cache lines, read through the same L2.
+__device__ inline unsigned xcd_block() {
+  constexpr unsigned kXcd = 8;
+  const unsigned b = blockIdx.x, G = gridDim.x;
+  const unsigned q = G / kXcd, r = G % kXcd, x = b % kXcd, i = b / kXcd;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // Marks every entry of a register array as modified (no code emitted).
 template <int J, int NM, typename T>
 __device__ __forceinline__ void opaque_regs(T (&a)[NM]) {
@@ -450,7 +460,7 @@ __global__ __launch_bounds__(SW * 64, 2) void small_fp64_kernel(int N, int64_t n
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
   if (threadIdx.x < SW) {
     const int64_t lim = list ? *count : n;
-    const int64_t slot = (int64_t)blockIdx.x * SW + threadIdx.x;
+    const int64_t slot = (int64_t)xcd_block() * SW + threadIdx.x;
     sst[threadIdx.x] = slot < lim ? (list ? list[slot] : slot) : -1;
   }
   __syncthreads();
@@ -493,7 +503,7 @@ __global__ __launch_bounds__(SW * 64, 2) void small_mixed_kernel(int N, int64_t 
   __shared__ int64_t sst[SW];                              // state of each wave, -1 if none
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
   if (threadIdx.x < SW) {
-    const int64_t slot = (int64_t)blockIdx.x * SW + threadIdx.x;
+    const int64_t slot = (int64_t)xcd_block() * SW + threadIdx.x;
     sst[threadIdx.x] = slot < n ? slot : -1;
   }
   __syncthreads();
