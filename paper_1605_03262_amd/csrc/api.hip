@@ -93,7 +93,7 @@ pyjac_status upload(pyjac_mech* m) {
   append(blob, P.rx, o);
   append(blob, P.eff_sp, o); append(blob, P.eff_am1, o); append(blob, P.plog, o); append(blob, P.cheb, o);
   append(blob, P.spg_ent, o);
-  append(blob, P.col_start, o); append(blob, P.colrec, o);
+  append(blob, P.col_start, o); append(blob, P.colrec, o); append(blob, P.col_order, o);
   if (hipMalloc(&m->dmem, blob.size()) != hipSuccess) return fail(PYJAC_E_NOMEM, "hipMalloc of mechanism tables failed");
   if (hipMemcpy(m->dmem, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess)
     return fail(PYJAC_E_DEVICE, "copy of mechanism tables failed");
@@ -108,7 +108,7 @@ pyjac_status upload(pyjac_mech* m) {
   d.eff_sp = D((const int*)0); d.eff_am1 = D((const double*)0); d.plog = D((const double*)0);
   d.cheb = D((const double*)0);
   d.spg_ent = D((const int*)0);
-  d.col_start = D((const int*)0); d.colrec = D((const ColRec*)0);
+  d.col_start = D((const int*)0); d.colrec = D((const ColRec*)0); d.col_order = D((const int*)0);
   d.spg_chunk = nullptr;
   return PYJAC_OK;
 }

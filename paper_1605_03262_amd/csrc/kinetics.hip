@@ -534,7 +534,8 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
   const double* aN = nasa_coeffs(md, N - 1, T);
   const double cpN = (aN[0] + T * (aN[1] + T * (aN[2] + T * (aN[3] + aN[4] * T)))) * kR * md.invW[N - 1];
   const double* Xb = lds + (size_t)L.X * TS + s;
-  for (int j = g; j < N - 1; j += Gr) {
+  for (int jc = g; jc < N - 1; jc += Gr) {
+    const int j = md.col_order[jc];
     // Column j: terms and row markers, read kColBatch records at a time with
     // independent loads; every record is evaluated without branching (markers
     // and padding have coef = 0) and a marker finishes the current row.

@@ -480,6 +480,14 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
       // one batch of slack: the kernel reads the batch after a column's last
       for (int u = 0; u < kColBatch; ++u) P.colrec.push_back(ColRec{0.0, -1, N | (N << 15)});
     }
+    // The groups of a wavefront stream their columns in lockstep, so columns
+    // go out longest first: neighbouring groups get streams of similar length.
+    P.col_order.resize(N - 1);
+    std::iota(P.col_order.begin(), P.col_order.end(), 0);
+    std::stable_sort(P.col_order.begin(), P.col_order.end(), [&](int a, int b) {
+      return P.col_start[a + 1] - P.col_start[a] > P.col_start[b + 1] - P.col_start[b];
+    });
+    if (P.col_order.empty()) P.col_order.push_back(0);
     return PYJAC_OK;
   } catch (const LoadError& e) {
     msg = e.what();

@@ -78,6 +78,7 @@ struct PackedMech {
                                                           // slot | nu << 16 (nu signed)
   std::vector<int> col_start;                             // [N] stream offsets per column
   std::vector<ColRec> colrec;
+  std::vector<int> col_order;                             // [N-1] columns, longest stream first
 };
 
 // Per-chunk bounds of the species reaction lists for reaction chunks of size
@@ -105,6 +106,7 @@ struct MechDev {
   const int* __restrict__ spg_chunk;    // species_chunk_bounds for the launch's chunk size
   const int* __restrict__ col_start;    // [N]
   const ColRec* __restrict__ colrec;
+  const int* __restrict__ col_order;    // [N-1] longest column stream first
 };
 
 }  // namespace pyjac
