@@ -158,7 +158,9 @@ def test_full_size_sampled(torch, Ref, cfg, n_sample):
     n = phi.shape[1]
     M = gpu_mech(mech)
     dphi_, dp = torch.from_numpy(phi).cuda(), torch.from_numpy(p).cuda()
-    J = M.eval_jacobian(dphi_, dp)
+    J = torch.empty((mech.n_species ** 2, n), dtype=torch.float64, device="cuda")
+    M.autotune(1, dphi_, dp, out=J, reps=1)          # the shape the benchmark would time
+    M.eval_jacobian(dphi_, dp, out=J)
     rng = np.random.default_rng(cfg)
     idx = np.unique(np.concatenate([[0, n - 1], rng.choice(n, n_sample, replace=False)]))
     Js = J[:, torch.from_numpy(idx).cuda()].cpu().numpy()

@@ -129,3 +129,39 @@ def test_newton_singular_nonfinite_and_workspace():
         _lib.pyjac_newton_factor_solve(M.handle, n, n, J.data_ptr(), h.data_ptr(), gamma, b.data_ptr(),
                                        x.data_ptr(), 1, 5, 1e-14, info.data_ptr(), ws.data_ptr(),
                                        ws.numel(), None)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("mode", [0, 1])
+def test_newton_full_size_backward_error(mode):
+    """The benchmark's full batch (100,000 states of the 53-species workload,
+    conditioned steps): for sampled states, the returned x solves the system
+    it was given, with an FP64 backward error at the level of a stable solve
+    (||b - A x|| <= 4 N u (||A|| ||x|| + ||b||), infinity norms, A = I - h gamma J
+    formed on the host from the same J)."""
+    import torch
+    from paper_1605_03262_amd import Mechanism
+    mech = config_mechanism(1)
+    N = mech.n_species
+    phi, p = config_states(1)
+    n = phi.shape[1]
+    M = Mechanism(text=mech.to_text())
+    d_phi, d_p = torch.from_numpy(phi).cuda(), torch.from_numpy(p).cuda()
+    J = M.eval_jacobian(d_phi, d_p)
+    rows = torch.abs(J.view(N, N, n)).sum(dim=1).cpu().numpy()
+    h = conditioned_steps(61, rows)
+    _, b = draw_newton_inputs(41, N, n)
+    x, info = M.newton_solve(J, torch.from_numpy(h).cuda(), torch.from_numpy(b).cuda(), NEWTON_GAMMA,
+                             mode=mode, max_refine=4, rtol=1e-14)
+    torch.cuda.synchronize()
+    info = info.cpu().numpy()
+    assert np.all((info == 0) if mode == 0 else ((info >= 1) | (info == -2))), np.unique(info)
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 200, replace=False)]))
+    Js = J[:, torch.from_numpy(idx).cuda()].cpu().numpy()
+    xs = x[:, torch.from_numpy(idx).cuda()].cpu().numpy()
+    for c, s in enumerate(idx):
+        A = np.eye(N) - h[s] * NEWTON_GAMMA * Js[:, c].reshape(N, N)
+        r = b[:, s].astype(np.longdouble) - A.astype(np.longdouble) @ xs[:, c].astype(np.longdouble)
+        bound = 4 * N * U * (np.abs(A).sum(axis=1).max() * np.abs(xs[:, c]).max() + np.abs(b[:, s]).max())
+        assert float(np.abs(r).max()) <= bound, (s, float(np.abs(r).max()), bound)
