@@ -106,8 +106,26 @@ def jacobian_only(cfg: int, steps: int) -> int:
     med, mean = time_stream(lambda: M.eval_jacobian(d_phi, d_p, out=jac), max(3, steps), torch)
     rmed, _ = time_stream(lambda: M.eval_rates(d_phi, d_p, rop_f=False, rop_r=False, pres_mod=False,
                                                wdot=False), max(3, steps), torch)
+    # Newton solve of the same batch, both modes, conditioned steps
+    from paper_1605_03262_amd import NEWTON_FP64, NEWTON_MIXED
+    from synth import NEWTON_GAMMA, conditioned_steps, draw_newton_inputs
+    M.eval_jacobian(d_phi, d_p, out=jac)
+    rows = torch.abs(jac.view(N, N, n)).sum(dim=1).cpu().numpy()
+    d_h = torch.from_numpy(conditioned_steps(3262 + 41, rows)).cuda()
+    d_b = torch.from_numpy(draw_newton_inputs(3262 + 40, N, n)[1]).cuda()
+    ws = torch.empty((max(M.newton_workspace_bytes(n, 0), M.newton_workspace_bytes(n, 1), 1),),
+                     dtype=torch.uint8, device="cuda")
+    newton = {}
+    for mode, name in ((NEWTON_FP64, "fp64_lu"), (NEWTON_MIXED, "fp32_lu_fp64_refine")):
+        run = lambda: M.newton_solve(jac, d_h, d_b, NEWTON_GAMMA, mode=mode, max_refine=4,  # noqa: E731
+                                     rtol=1e-14, workspace=ws)
+        nmed, _ = time_stream(run, 3, torch)
+        _, info = run()
+        torch.cuda.synchronize()
+        newton[name] = {"ms_median": nmed, "fallbacks": int((info[:n] == -2).sum().item())}
+    newton["mixed_speedup"] = newton["fp64_lu"]["ms_median"] / newton["fp32_lu_fp64_refine"]["ms_median"]
     by = n * (8.0 * N * N + 8.0 * (N + 1))
-    print(json.dumps({"workload": CONFIGS[cfg]["name"], "n_states": n, "n_species": N,
+    print(json.dumps({"workload": CONFIGS[cfg]["name"], "n_states": n, "n_species": N, "newton": newton,
                       "jacobian_ms_median": med, "jacobian_evals_per_s": n / (med * 1e-3),
                       "hbm_frac": by / (med * 1e-3) / 1e9 / HBM_PEAK_GBS,
                       "rhs_ms_median": rmed, "rhs_evals_per_s": n / (rmed * 1e-3),
