@@ -687,9 +687,11 @@ __global__ __launch_bounds__(256) void solve_kernel(int N, int64_t n, int64_t ld
   if (lane == 0 && sweep > 0 && fin && dmax <= rtol * xmax) status[st] = sweep;
 }
 
-// r = b - (I - h gamma J) x in FP64, one thread per state, rows in blocks of
-// 8 so each x_j load serves 8 multiply-adds; every load is coalesced across
-// the states of a wavefront.  Converged states are skipped.
+// r = b - (I - h gamma J) x in FP64.  grid (ceil(n / 256), ceil(N / 8)): one
+// thread per (state, block of 8 rows), so that a few thousand states still
+// fill the device; each x_j load serves 8 multiply-adds and every load is
+// coalesced across the states of a wavefront.  Converged states are skipped.
+constexpr int kResRows = 8;
 __global__ __launch_bounds__(256) void residual_kernel(int N, int64_t n, int64_t ld, const double* __restrict__ jac,
                                                        const double* __restrict__ h, double gamma,
                                                        const double* __restrict__ rhs, const double* __restrict__ xs,
@@ -697,8 +699,9 @@ __global__ __launch_bounds__(256) void residual_kernel(int N, int64_t n, int64_t
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n || status[s] != ST_UNSET) return;
   const double hg = h[s] * gamma;
-  constexpr int IB = 8;
-  for (int i0 = 0; i0 < N; i0 += IB) {
+  constexpr int IB = kResRows;
+  {
+    const int i0 = blockIdx.y * IB;
     double acc[IB];
 #pragma unroll
     for (int u = 0; u < IB; ++u) acc[u] = 0.0;
@@ -882,7 +885,8 @@ pyjac_status pyjac_newton_factor_solve(const pyjac_mech* m, int64_t n, int64_t l
     const unsigned gs = (unsigned)((n + 3) / 4);
     for (int sweep = 0; sweep <= max_refine; ++sweep) {
       if (sweep > 0)
-        hipLaunchKernelGGL(residual_kernel, dim3(g1), dim3(256), 0, st, N, n, ld, jac, h, gamma, rhs, (const double*)xs,
+        hipLaunchKernelGGL(residual_kernel, dim3(g1, (unsigned)((N + kResRows - 1) / kResRows)), dim3(256), 0, st, N,
+                           n, ld, jac, h, gamma, rhs, (const double*)xs,
                            rbuf, (const int*)status);
       hipLaunchKernelGGL((solve_kernel<float, true>), dim3(gs), dim3(256), 4 * N * sizeof(float), st, N, n, ld,
                          (const float*)A32, (const int*)piv, (const double*)nullptr, (const double*)rbuf, xs,
