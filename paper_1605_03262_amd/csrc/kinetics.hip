@@ -48,7 +48,7 @@ struct TileLayout {
   int rows;                      // total rows
   __host__ __device__ TileLayout(int N, int NR, int NG, int Gr, bool jac) {
     X = 0;
-    KF = X + N + 1;                         // must directly follow X (padding reads X[N] as P[-1])
+    KF = X + N + 1;                         // must directly follow X: column streams index both from X
     KR = KF + (jac ? NR : 0);
     G = KR + (jac ? NR : 0);
     SC = G + (jac ? NG : 0);
@@ -528,7 +528,6 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
 
   // ---- phase D: temperature column, species columns with the temperature row
   const double Shw = SC[SC_SHW * TS];
-  const double* P = KF;     // KF, KR, G are contiguous
   if (live)
     for (int k = g; k < N - 1; k += Gr) jac[(int64_t)((k + 1) * N) * ld + sg] = JT[k * TS];
   const double* aN = nasa_coeffs(md, N - 1, T);
@@ -558,11 +557,18 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
       ColRec nx[kColBatch];
 #pragma unroll
       for (int u = 0; u < kColBatch; ++u) nx[u] = rec[b + kColBatch + u];
+      // the batch's products first, with no branch between them, so that all
+      // their LDS reads are in flight together; then the row bookkeeping
+      double t[kColBatch];
 #pragma unroll
       for (int u = 0; u < kColBatch; ++u) {
         const int x = r[u].x;
-        val += r[u].coef * P[r[u].src * TS] * Xb[(x & 0x7FFF) * TS] * Xb[((x >> 15) & 0x7FFF) * TS];
-        if (x & kColMark) {
+        t[u] = r[u].coef * Xb[r[u].src * TS] * Xb[(x & 0x7FFF) * TS] * Xb[((x >> 15) & 0x7FFF) * TS];
+      }
+#pragma unroll
+      for (int u = 0; u < kColBatch; ++u) {
+        val += t[u];
+        if (r[u].x & kColMark) {
           if (k < N - 1 && live) *outp = val;
           TR += hk * val;
           outp += rstride;

@@ -467,18 +467,17 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
         P.col_start.push_back((int)P.colrec.size());
         for (int k = 0; k < N; ++k) {
           while (t < terms.size() && terms[t].j == j && terms[t].k == k) {
-            P.colrec.push_back(ColRec{terms[t].coef, terms[t].src, terms[t].x});
+            P.colrec.push_back(ColRec{terms[t].coef, N + 1 + terms[t].src, terms[t].x});
             ++t;
           }
-          // end of row k; src -1 addresses X[N] = 1 (the LDS row just below P),
-          // so markers and padding always contribute exactly 0
-          P.colrec.push_back(ColRec{0.0, -1, N | (N << 15) | kColMark});
+          // end of row k; markers and padding address X[N] = 1 and contribute 0
+          P.colrec.push_back(ColRec{0.0, N, N | (N << 15) | kColMark});
         }
-        while (P.colrec.size() % kColBatch) P.colrec.push_back(ColRec{0.0, -1, N | (N << 15)});
+        while (P.colrec.size() % kColBatch) P.colrec.push_back(ColRec{0.0, N, N | (N << 15)});
       }
       P.col_start.push_back((int)P.colrec.size());
       // one batch of slack: the kernel reads the batch after a column's last
-      for (int u = 0; u < kColBatch; ++u) P.colrec.push_back(ColRec{0.0, -1, N | (N << 15)});
+      for (int u = 0; u < kColBatch; ++u) P.colrec.push_back(ColRec{0.0, N, N | (N << 15)});
     }
     // The groups of a wavefront stream their columns in lockstep, so columns
     // go out longest first: neighbouring groups get streams of similar length.

@@ -51,10 +51,11 @@ struct alignas(16) RxnRec {
 static_assert(sizeof(RxnRec) == 256, "RxnRec must stay 256 bytes");
 
 // One entry of a Jacobian column stream.  Every entry contributes
-// coef * P[src] * X[x & 0x7FFF] * X[(x >> 15) & 0x7FFF] to the current element
-// (coef = 0 for markers and padding, whose src = -1 addresses the constant
-// X[N] = 1 stored just below P); an entry with bit kColMark set in x ends
-// the current row.  Column j's stream holds, for rows k = 0..N-1 in order, the
+// coef * X[src] * X[x & 0x7FFF] * X[(x >> 15) & 0x7FFF] to the current element,
+// where X[0..N] are the concentrations (X[N] = 1) and the rate products P
+// follow directly, so src = N + 1 + (index into P).  Markers and padding have
+// coef = 0 and src = N; an entry with bit kColMark set in x ends the current
+// row.  Column j's stream holds, for rows k = 0..N-1 in order, the
 // terms of (k, j) followed by one marker, then padding to a multiple of
 // kColBatch.
 struct alignas(16) ColRec {
@@ -62,7 +63,7 @@ struct alignas(16) ColRec {
   int src, x;
 };
 constexpr int kColMark = 1 << 30;
-constexpr int kColBatch = 8;
+constexpr int kColBatch = 4;
 
 // Host-side packed tables (sorted reaction order).
 struct PackedMech {

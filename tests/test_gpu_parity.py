@@ -216,8 +216,10 @@ def test_launch_shape_does_not_change_results(torch):
 
 
 def test_autotune_keeps_fastest_and_results(torch):
-    """The autotuner times every shape that fits, keeps the fastest median,
-    and (shape independence) leaves every result bitwise unchanged."""
+    """The autotuner times every shape that fits and keeps a shape whose
+    median is within its 2% switching margin of the fastest (a shape replaces
+    the current choice only when it is more than 2% faster); by shape
+    independence every result stays bitwise unchanged."""
     mech = config_mechanism(1)
     phi, p = config_states(1, 3000)
     M = gpu_mech(mech)
@@ -227,9 +229,11 @@ def test_autotune_keeps_fastest_and_results(torch):
     for which in (1, 0):
         rep = M.autotune(which, d_phi, d_p, reps=3)
         assert len(rep) >= 2
-        best = min(rep, key=lambda e: e[1])[0]
+        best_ms = min(e[1] for e in rep)
         ts, nt, _ = M.get_variant(which)
-        assert (ts, nt) == best
+        kept = [e[1] for e in rep if tuple(e[0]) == (ts, nt)]
+        assert len(kept) == 1
+        assert kept[0] * 0.98 <= best_ms * (1 + 1e-6)
     assert np.array_equal(base_j, gpu_jac(torch, M, phi, p))
     r = gpu_rates(torch, M, phi, p)
     for k in r:
