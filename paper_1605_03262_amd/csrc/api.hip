@@ -94,6 +94,7 @@ pyjac_status upload(pyjac_mech* m) {
   append(blob, P.eff_sp, o); append(blob, P.eff_am1, o); append(blob, P.plog, o); append(blob, P.cheb, o);
   append(blob, P.spg_ent, o);
   append(blob, P.col_start, o); append(blob, P.colrec, o); append(blob, P.col_order, o);
+  append(blob, P.col_flags, o);
   if (hipMalloc(&m->dmem, blob.size()) != hipSuccess) return fail(PYJAC_E_NOMEM, "hipMalloc of mechanism tables failed");
   if (hipMemcpy(m->dmem, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess)
     return fail(PYJAC_E_DEVICE, "copy of mechanism tables failed");
@@ -101,7 +102,7 @@ pyjac_status upload(pyjac_mech* m) {
   size_t q = 0;
   auto D = [&](auto ptr_type) { return reinterpret_cast<decltype(ptr_type)>(b + o[q++]); };
   MechDev& d = m->dev;
-  d.N = P.N; d.NR = P.NR; d.NG = P.NG;
+  d.N = P.N; d.NR = P.NR; d.NG = P.NG; d.col_split = P.col_split;
   d.W = D((const double*)0); d.invW = D((const double*)0); d.nasa = D((const double*)0);
   d.tmid = D((const double*)0); d.vcol = D((const double*)0);
   d.rx = D((const RxnRec*)0);
@@ -109,6 +110,7 @@ pyjac_status upload(pyjac_mech* m) {
   d.cheb = D((const double*)0);
   d.spg_ent = D((const int*)0);
   d.col_start = D((const int*)0); d.colrec = D((const ColRec*)0); d.col_order = D((const int*)0);
+  d.col_flags = D((const uint32_t*)0);
   d.spg_chunk = nullptr;
   return PYJAC_OK;
 }

@@ -38,7 +38,7 @@ constexpr double kR = kGasConstant;
 constexpr double kLn10 = 2.302585092994045684;
 constexpr double kInvLn10 = 0.4342944819032518277;
 constexpr int NSC = 16;
-enum { SC_T = 0, SC_IT, SC_LT, SC_P, SC_LP, SC_L10P, SC_RHO, SC_W, SC_M, SC_CP, SC_DCP, SC_SHW, SC_J00 };
+enum { SC_T = 0, SC_IT, SC_LT, SC_P, SC_LP, SC_L10P, SC_RHO, SC_W, SC_M, SC_CP, SC_DCP, SC_SHW, SC_J00, SC_HA, SC_HB };
 
 // LDS layout in doubles; each entry counts rows of TS doubles.
 struct TileLayout {
@@ -319,7 +319,9 @@ __device__ inline unsigned xcd_tile() {
   return x * q + (x < r ? x : r) + i;
 }
 
-template <int TS, int NT, int KPT, bool JAC>
+// SPLIT selects the form of the Jacobian column streams: every row streamed
+// (false) or only the rows with terms, the others written by a dense pass (true).
+template <int TS, int NT, int KPT, bool JAC, bool SPLIT>
 __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev md, int64_t n, int64_t ld,
                                                   const double* __restrict__ phi,
                                                   const double* __restrict__ pin,
@@ -327,6 +329,7 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
                                                   double* __restrict__ pmod, double* __restrict__ wdot_out,
                                                   double* __restrict__ dphi_out, double* __restrict__ jac) {
   constexpr int Gr = NT / TS;
+  static_assert(Gr >= 3, "the per-state sums of phase C use three index groups");
   extern __shared__ double lds[];
   const int N = md.N, NR = md.NR, NG = md.NG;
   const int tid = threadIdx.x, s = tid % TS, g = tid / TS;
@@ -513,6 +516,10 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
     }
   }
   __syncthreads();
+  // per-state sums over species, each formed by one thread in species order;
+  // with split column streams two more threads form the sums of h_k times the
+  // two dense coefficients, which give the dense part's share of every
+  // temperature-row entry in closed form
   if (g == 0) {
     double a0 = 0.0, a1 = 0.0;
     for (int k = 0; k < N; ++k) {
@@ -522,12 +529,17 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
     SC[SC_SHW * TS] = a0;
     if (!JAC && live && dphi_out) dphi_out[sg] = -a0 / (rho * cp);
     if (JAC && live) jac[sg] = -a1 / cp;
+  } else if (SPLIT && g < 3) {
+    double a = 0.0;
+    for (int k = 0; k < N; ++k) a += H[k * TS] * (g == 1 ? WAB[k * TS].x : WAB[k * TS].y);
+    SC[(g == 1 ? SC_HA : SC_HB) * TS] = a;
   }
   if (!JAC) return;
   __syncthreads();
 
   // ---- phase D: temperature column, species columns with the temperature row
   const double Shw = SC[SC_SHW * TS];
+  const double HA = SPLIT ? SC[SC_HA * TS] : 0.0, HB = SPLIT ? SC[SC_HB * TS] : 0.0;
   if (live)
     for (int k = g; k < N - 1; k += Gr) jac[(int64_t)((k + 1) * N) * ld + sg] = JT[k * TS];
   const double* aN = nasa_coeffs(md, N - 1, T);
@@ -535,52 +547,139 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
   const double* Xb = lds + (size_t)L.X * TS + s;
   for (int jc = g; jc < N - 1; jc += Gr) {
     const int j = md.col_order[jc];
-    // Column j: terms and row markers, read kColBatch records at a time with
-    // independent loads; every record is evaluated without branching (markers
-    // and padding have coef = 0) and a marker finishes the current row.
     const double vj = md.vcol[j];
-    const ColRec* rec = md.colrec + md.col_start[j];
-    const int cnt = md.col_start[j + 1] - md.col_start[j];
-    double* outp = jac + (int64_t)(N + j + 1) * ld + sg;       // element (1, j+1)
-    const int64_t rstride = (int64_t)N * ld;
-    double TR = 0.0;
-    double2 ab = WAB[0];
-    double val = ab.x * vj + ab.y;
-    double hk = H[0];
-    double2 abn = WAB[(N > 1 ? 1 : 0) * TS];
-    int k = 0;
-    ColRec r[kColBatch];
+    double TR;
+    if constexpr (!SPLIT) {
+      // Column j, every row streamed: terms and one marker per row, read
+      // kColBatch records at a time with independent loads; every record is
+      // evaluated without branching (markers and padding have coef = 0) and a
+      // marker finishes the current row and starts the next.
+      const ColRec* rec = md.colrec + md.col_start[j];
+      const int cnt = md.col_start[j + 1] - md.col_start[j];
+      double* outp = jac + (int64_t)(N + j + 1) * ld + sg;       // element (1, j+1)
+      const int64_t rstride = (int64_t)N * ld;
+      TR = 0.0;
+      double2 ab = WAB[0];
+      double val = ab.x * vj + ab.y;
+      double hk = H[0];
+      double2 abn = WAB[(N > 1 ? 1 : 0) * TS];
+      int k = 0;
+      ColRec r[kColBatch];
 #pragma unroll
-    for (int u = 0; u < kColBatch; ++u) r[u] = rec[u];
-    for (int b = 0; b < cnt; b += kColBatch) {
-      // the stream carries one batch of slack, so the next batch is always readable
-      ColRec nx[kColBatch];
+      for (int u = 0; u < kColBatch; ++u) r[u] = rec[u];
+      for (int b = 0; b < cnt; b += kColBatch) {
+        // the table carries one batch of slack, so the next batch is always readable
+        ColRec nx[kColBatch];
 #pragma unroll
-      for (int u = 0; u < kColBatch; ++u) nx[u] = rec[b + kColBatch + u];
-      // the batch's products first, with no branch between them, so that all
-      // their LDS reads are in flight together; then the row bookkeeping
-      double t[kColBatch];
+        for (int u = 0; u < kColBatch; ++u) nx[u] = rec[b + kColBatch + u];
+        // the batch's products first, with no branch between them, so that all
+        // their LDS reads are in flight together; then the row bookkeeping
+        double t[kColBatch];
 #pragma unroll
-      for (int u = 0; u < kColBatch; ++u) {
-        const int x = r[u].x;
-        t[u] = r[u].coef * Xb[r[u].src * TS] * Xb[(x & 0x7FFF) * TS] * Xb[((x >> 15) & 0x7FFF) * TS];
+        for (int u = 0; u < kColBatch; ++u) {
+          const int x = r[u].x;
+          t[u] = r[u].coef * Xb[r[u].src * TS] * Xb[(x & 0x7FFF) * TS] * Xb[((x >> 15) & 0x7FFF) * TS];
+        }
+#pragma unroll
+        for (int u = 0; u < kColBatch; ++u) {
+          val += t[u];
+          if (r[u].x & kColMark) {
+            if (k < N - 1 && live) *outp = val;
+            TR += hk * val;
+            outp += rstride;
+            ++k;
+            val = abn.x * vj + abn.y;
+            const int kn = k + 1 < N ? k + 1 : N - 1;
+            hk = H[min(k, N - 1) * TS];
+            abn = WAB[kn * TS];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kColBatch; ++u) r[u] = nx[u];
       }
+    } else {
+      double* colp = jac + (int64_t)(N + j + 1) * ld + sg;       // element (1, j+1): row k = 0
+      const int64_t rstride = (int64_t)N * ld;
+      const int FW = colFlagWords(N);
+      // temperature row: sum_k h_k J[k][j], the dense part in closed form here,
+      // the terms of the present rows added by the stream below
+      TR = vj * HA + HB;
+      // Rows without column-stream terms hold the dense part W_k (A_k v_j + B_k)/rho
+      // alone.  This pass visits the rows of every 32-row block that has rows
+      // not flagged present, in the same order in all lanes, and stores those
+      // rows; the present rows are left to the stream.
+      const uint32_t* fl = md.col_flags + (size_t)j * FW;
+      for (int k0 = 0; k0 < N; k0 += 32) {
+        const uint32_t f = fl[k0 >> 5];
+        const int kn = min(32, N - k0);
+        // rows to store: not present, below the placeholder row N - 1, in range
+        uint32_t st = ~f & (kn == 32 ? 0xFFFFFFFFu : (1u << kn) - 1u);
+        if (st == 0u) continue;
+        if (k0 + kn > N - 1) st &= ~(1u << (N - 1 - k0));
+        if (!live) st = 0u;
+        for (int kk = 0; kk < kn; kk += 4) {
+          // four rows read before any store, so the reads overlap (the empty
+          // asm keeps the compiler from moving each read into its store branch)
+          double2 ab[4];
 #pragma unroll
-      for (int u = 0; u < kColBatch; ++u) {
-        val += t[u];
-        if (r[u].x & kColMark) {
-          if (k < N - 1 && live) *outp = val;
-          TR += hk * val;
-          outp += rstride;
-          ++k;
-          val = abn.x * vj + abn.y;
-          const int kn = k + 1 < N ? k + 1 : N - 1;
-          hk = H[min(k, N - 1) * TS];
-          abn = WAB[kn * TS];
+          for (int u = 0; u < 4; ++u) ab[u] = WAB[min(k0 + kk + u, N - 1) * TS];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) asm volatile("" : "+v"(ab[u].x), "+v"(ab[u].y));
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if ((st >> (kk + u)) & 1u) colp[(k0 + kk + u) * rstride] = ab[u].x * vj + ab[u].y;
         }
       }
+      // Present rows: the column stream, kColBatch records at a time with
+      // independent loads.  Every record's product is formed without branching
+      // (markers and padding have coef = 0); a marker ends the open row, storing
+      // its terms plus the dense part and adding h_k times its terms to the
+      // temperature row, and opens the row it names.  No row is open at the
+      // start (k = N: nothing is stored and hk = 0).
+      const ColRec* rec = md.colrec + md.col_start[j];
+      const int cnt = md.col_start[j + 1] - md.col_start[j];
+      double val = 0.0, hk = 0.0;
+      double2 ab = make_double2(0.0, 0.0);
+      int k = N;
+      // one batch: the products first, with no branch between them, so that all
+      // their LDS reads are in flight together; then the row bookkeeping
+      auto batch = [&](const ColRec (&r)[kColBatch]) {
+        double t[kColBatch];
 #pragma unroll
-      for (int u = 0; u < kColBatch; ++u) r[u] = nx[u];
+        for (int u = 0; u < kColBatch; ++u) {
+          const int x = r[u].x;
+          t[u] = r[u].coef * Xb[r[u].src * TS] * Xb[(x & 0x7FFF) * TS] * Xb[((x >> 15) & 0x7FFF) * TS];
+        }
+#pragma unroll
+        for (int u = 0; u < kColBatch; ++u) {
+          val += t[u];
+          if (r[u].x & kColMark) {
+            if (k < N - 1 && live) colp[k * rstride] = val + (ab.x * vj + ab.y);
+            TR += hk * val;
+            k = r[u].src;
+            val = 0.0;
+            // k = N after the last present row: only zero terms follow, so the
+            // clamped reads are never used
+            const int kc = min(k, N - 1);
+            ab = WAB[kc * TS];
+            hk = H[kc * TS];
+          }
+        }
+      };
+      // Two record buffers in turn: each batch's loads are issued one batch of
+      // work ahead.  Streams are padded to a multiple of two batches, and one
+      // batch of slack follows the last, so every load stays inside the table.
+      ColRec ra[kColBatch], rb[kColBatch];
+#pragma unroll
+      for (int u = 0; u < kColBatch; ++u) ra[u] = rec[u];
+      for (int b = 0; b < cnt; b += 2 * kColBatch) {
+#pragma unroll
+        for (int u = 0; u < kColBatch; ++u) rb[u] = rec[b + kColBatch + u];
+        batch(ra);
+#pragma unroll
+        for (int u = 0; u < kColBatch; ++u) ra[u] = rec[b + 2 * kColBatch + u];
+        batch(rb);
+      }
     }
     const double* aj = nasa_coeffs(md, j, T);
     const double cpj = (aj[0] + T * (aj[1] + T * (aj[2] + T * (aj[3] + aj[4] * T)))) * kR * md.invW[j];
@@ -594,11 +693,11 @@ size_t tile_lds_bytes(int N, int NR, int NG, int TS, int NT, bool jac) {
   return (size_t)L.rows * TS * sizeof(double);
 }
 
-template <int TS, int NT, int KPT, bool JAC>
+template <int TS, int NT, int KPT, bool JAC, bool SPLIT>
 static hipError_t launch_t(const MechDev& md, int64_t n, int64_t ld, const double* phi, const double* p,
                            double* a, double* b, double* c, double* d, double* e, double* jac,
                            size_t lds, hipStream_t st) {
-  auto kern = tile_kernel<TS, NT, KPT, JAC>;
+  auto kern = tile_kernel<TS, NT, KPT, JAC, SPLIT>;
   hipError_t err = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
   const int64_t tiles = (n + TS - 1) / TS;
@@ -606,14 +705,14 @@ static hipError_t launch_t(const MechDev& md, int64_t n, int64_t ld, const doubl
   return hipGetLastError();
 }
 
-template <int TS, int NT, bool JAC>
+template <int TS, int NT, bool JAC, bool SPLIT>
 static hipError_t launch_k(int kpt, const MechDev& md, int64_t n, int64_t ld, const double* phi,
                            const double* p, double* a, double* b, double* c, double* d, double* e,
                            double* jac, size_t lds, hipStream_t st) {
-  if (kpt <= 1) return launch_t<TS, NT, 1, JAC>(md, n, ld, phi, p, a, b, c, d, e, jac, lds, st);
-  if (kpt <= 2) return launch_t<TS, NT, 2, JAC>(md, n, ld, phi, p, a, b, c, d, e, jac, lds, st);
-  if (kpt <= 4) return launch_t<TS, NT, 4, JAC>(md, n, ld, phi, p, a, b, c, d, e, jac, lds, st);
-  if (kpt <= 8) return launch_t<TS, NT, 8, JAC>(md, n, ld, phi, p, a, b, c, d, e, jac, lds, st);
+  if (kpt <= 1) return launch_t<TS, NT, 1, JAC, SPLIT>(md, n, ld, phi, p, a, b, c, d, e, jac, lds, st);
+  if (kpt <= 2) return launch_t<TS, NT, 2, JAC, SPLIT>(md, n, ld, phi, p, a, b, c, d, e, jac, lds, st);
+  if (kpt <= 4) return launch_t<TS, NT, 4, JAC, SPLIT>(md, n, ld, phi, p, a, b, c, d, e, jac, lds, st);
+  if (kpt <= 8) return launch_t<TS, NT, 8, JAC, SPLIT>(md, n, ld, phi, p, a, b, c, d, e, jac, lds, st);
   return hipErrorInvalidValue;
 }
 
@@ -624,8 +723,9 @@ hipError_t launch_tile(bool jac_mode, int TS, int NT, const MechDev& md, int64_t
   const int kpt = (md.N + NT / TS - 1) / (NT / TS);
 #define PYJAC_VARIANT(ts, nt)                                                                          \
   if (TS == ts && NT == nt)                                                                            \
-    return jac_mode ? launch_k<ts, nt, true>(kpt, md, n, ld, phi, p, rop_f, rop_r, pmod, wdot, dphi, jac, lds, st) \
-                    : launch_k<ts, nt, false>(kpt, md, n, ld, phi, p, rop_f, rop_r, pmod, wdot, dphi, jac, lds, st);
+    return !jac_mode ? launch_k<ts, nt, false, false>(kpt, md, n, ld, phi, p, rop_f, rop_r, pmod, wdot, dphi, jac, lds, st) \
+         : md.col_split ? launch_k<ts, nt, true, true>(kpt, md, n, ld, phi, p, rop_f, rop_r, pmod, wdot, dphi, jac, lds, st) \
+                        : launch_k<ts, nt, true, false>(kpt, md, n, ld, phi, p, rop_f, rop_r, pmod, wdot, dphi, jac, lds, st);
   PYJAC_VARIANT(16, 1024)
   PYJAC_VARIANT(16, 512)
   PYJAC_VARIANT(32, 1024)

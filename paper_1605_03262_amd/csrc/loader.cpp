@@ -461,22 +461,65 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
       return a.j != b.j ? a.j < b.j : a.k < b.k;
     });
 
+    const int FW = colFlagWords(N);
+    P.col_flags.assign((size_t)std::max(N - 1, 1) * FW, 0u);
     {
+      // form of the streams: present rows only when most (row, column) pairs
+      // have no terms, every row otherwise
+      long long pairs = 0;
+      for (size_t u = 0; u < terms.size(); ++u)
+        pairs += (u == 0 || terms[u].j != terms[u - 1].j || terms[u].k != terms[u - 1].k);
+      P.col_split = 2 * pairs < (long long)(N - 1) * N ? 1 : 0;
+    }
+    if (!P.col_split) {
       size_t t = 0;
       for (int j = 0; j < N - 1; ++j) {
         P.col_start.push_back((int)P.colrec.size());
         for (int k = 0; k < N; ++k) {
-          while (t < terms.size() && terms[t].j == j && terms[t].k == k) {
+          for (; t < terms.size() && terms[t].j == j && terms[t].k == k; ++t)
             P.colrec.push_back(ColRec{terms[t].coef, N + 1 + terms[t].src, terms[t].x});
-            ++t;
-          }
           // end of row k; markers and padding address X[N] = 1 and contribute 0
           P.colrec.push_back(ColRec{0.0, N, N | (N << 15) | kColMark});
         }
         while (P.colrec.size() % kColBatch) P.colrec.push_back(ColRec{0.0, N, N | (N << 15)});
       }
       P.col_start.push_back((int)P.colrec.size());
-      // one batch of slack: the kernel reads the batch after a column's last
+      // one batch of slack: the kernel reads one batch past a column's stream
+      for (int u = 0; u < kColBatch; ++u) P.colrec.push_back(ColRec{0.0, N, N | (N << 15)});
+    } else {
+      size_t t = 0;
+      for (int j = 0; j < N - 1; ++j) {
+        P.col_start.push_back((int)P.colrec.size());
+        // rows of column j with terms.  A row without terms costs a marker in
+        // the stream but a full visit in the dense pass, so a block of 32 rows
+        // goes to the dense pass only when most of its rows have no terms;
+        // otherwise all its rows are streamed.
+        std::vector<char> has(N, 0);
+        for (size_t u = t; u < terms.size() && terms[u].j == j; ++u) has[terms[u].k] = 1;
+        std::vector<int> rows;
+        for (int w = 0; w < FW; ++w) {
+          const int k0 = 32 * w, kn = std::min(32, N - k0);
+          int absent = 0;
+          for (int k = k0; k < k0 + kn; ++k) absent += !has[k];
+          const bool split = 2 * absent > kn;
+          for (int k = k0; k < k0 + kn; ++k)
+            if (has[k] || !split) {
+              rows.push_back(k);
+              P.col_flags[(size_t)j * FW + w] |= 1u << (k - k0);
+            }
+        }
+        P.colrec.push_back(ColRec{0.0, rows.empty() ? N : rows[0], N | (N << 15) | kColMark});
+        for (size_t q = 0; q < rows.size(); ++q) {
+          for (; t < terms.size() && terms[t].j == j && terms[t].k == rows[q]; ++t)
+            P.colrec.push_back(ColRec{terms[t].coef, N + 1 + terms[t].src, terms[t].x});
+          const int next = q + 1 < rows.size() ? rows[q + 1] : N;
+          P.colrec.push_back(ColRec{0.0, next, N | (N << 15) | kColMark});
+        }
+        // padding addresses X[N] = 1 and contributes 0
+        while (P.colrec.size() % (2 * kColBatch)) P.colrec.push_back(ColRec{0.0, N, N | (N << 15)});
+      }
+      P.col_start.push_back((int)P.colrec.size());
+      // one batch of slack: the kernel reads one batch past a column's stream
       for (int u = 0; u < kColBatch; ++u) P.colrec.push_back(ColRec{0.0, N, N | (N << 15)});
     }
     // The groups of a wavefront stream their columns in lockstep, so columns

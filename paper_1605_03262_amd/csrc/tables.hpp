@@ -53,11 +53,19 @@ static_assert(sizeof(RxnRec) == 256, "RxnRec must stay 256 bytes");
 // One entry of a Jacobian column stream.  Every entry contributes
 // coef * X[src] * X[x & 0x7FFF] * X[(x >> 15) & 0x7FFF] to the current element,
 // where X[0..N] are the concentrations (X[N] = 1) and the rate products P
-// follow directly, so src = N + 1 + (index into P).  Markers and padding have
-// coef = 0 and src = N; an entry with bit kColMark set in x ends the current
-// row.  Column j's stream holds, for rows k = 0..N-1 in order, the
-// terms of (k, j) followed by one marker, then padding to a multiple of
-// kColBatch.
+// follow directly, so src = N + 1 + (index into P).  A marker has bit kColMark
+// set in x and coef = 0; padding has coef = 0 and src = N.  Two forms:
+//  * every row (col_split = 0): for rows k = 0..N-1 in order, the terms of
+//    (k, j) and a marker (src = N) that ends row k; padding to a multiple of
+//    kColBatch.
+//  * present rows only (col_split = 1): bit k of the column's col_flags words
+//    marks row k as present (streamed); the other rows hold the dense part
+//    alone.  The stream is a marker, then for each present row in ascending
+//    order its terms and a marker, padded to a multiple of 2 kColBatch; a
+//    marker's src is the next present row (N after the last): it ends the open
+//    row and opens that one.
+// The loader takes the second form when most (row, column) pairs have no
+// terms (large mechanisms), where it saves a marker per empty row.
 struct alignas(16) ColRec {
   double coef;
   int src, x;
@@ -80,7 +88,11 @@ struct PackedMech {
   std::vector<int> col_start;                             // [N] stream offsets per column
   std::vector<ColRec> colrec;
   std::vector<int> col_order;                             // [N-1] columns, longest stream first
+  std::vector<uint32_t> col_flags;                        // [N-1][colFlagWords(N)] present rows
+  int col_split = 0;                                      // column-stream form (see ColRec)
 };
+
+constexpr int colFlagWords(int N) { return (N + 31) / 32; }
 
 // Per-chunk bounds of the species reaction lists for reaction chunks of size
 // `chunk`: entry [c * N + k] is the first list index of species k whose
@@ -93,6 +105,7 @@ int build_tables(const std::string& text, PackedMech& out, std::string& msg);
 // Device view (all pointers into one device allocation).
 struct MechDev {
   int N, NR, NG;
+  int col_split;                        // column-stream form (see ColRec)
   const double* __restrict__ W;
   const double* __restrict__ invW;
   const double* __restrict__ nasa;      // [N][2][7]
@@ -108,6 +121,7 @@ struct MechDev {
   const int* __restrict__ col_start;    // [N]
   const ColRec* __restrict__ colrec;
   const int* __restrict__ col_order;    // [N-1] longest column stream first
+  const uint32_t* __restrict__ col_flags;  // [N-1][colFlagWords(N)]
 };
 
 }  // namespace pyjac

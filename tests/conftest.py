@@ -31,3 +31,15 @@ def tiny(seed, kinds, n_species=7, reactive_last=False, rev_mix=None, allow_shar
                           rev_mix=rev_mix or {"kc": 1.0}, elements=("H", "O"),
                           bounds={"H": 3, "O": 3}, allow_shared=allow_shared,
                           collider_probs=collider_probs)
+
+
+def split_form_mech(seed, reactive_last=False):
+    """40 species, one reaction of every class plus elementary ones: most
+    (row, column) pairs of the Jacobian have no terms, and the species span two
+    32-row blocks."""
+    from synth import tiny_mechanism
+    kinds = {k: 1 for k in ALL_KINDS}
+    kinds["elementary"] += 3
+    return tiny_mechanism(seed, kinds, n_species=40, reactive_last=reactive_last,
+                          rev_mix={"kc": 2, "explicit": 1, "irrev": 1},
+                          elements=("C", "H", "O", "N"), bounds={"C": 2, "H": 5, "O": 3, "N": 1})

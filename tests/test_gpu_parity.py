@@ -12,7 +12,7 @@ import os
 import numpy as np
 import pytest
 
-from conftest import ALL_KINDS, tiny
+from conftest import ALL_KINDS, split_form_mech, tiny
 from synth import ATM, config_mechanism, config_states, draw_states
 
 pytestmark = pytest.mark.gpu
@@ -132,6 +132,31 @@ def test_tiny_parity(torch, Ref, name, kinds, rev):
     M = gpu_mech(mech)
     check_rates(gpu_rates(torch, M, phi, p, ld=83), ref.eval_rates(phi, p), mech, phi, p, name)
     check_jac(gpu_jac(torch, M, phi, p, ld=83), ref.eval_jacobian(phi, p), name)
+
+
+# ----------------------------------------- column streams of present rows only
+@pytest.mark.parametrize("seed,last", [(11, False), (12, True)])
+def test_split_form_parity_and_shapes(torch, Ref, seed, last):
+    """A sparse 40-species mechanism (streams of present rows plus the dense
+    pass, over two 32-row blocks): oracle parity, and bitwise the same
+    results in every launch shape."""
+    mech = split_form_mech(seed, reactive_last=last)
+    phi, p = draw_states(seed, mech.n_species, 150, T=(700.0, 2400.0), P_atm=(0.3, 80.0),
+                         dirichlet=0.5)
+    ref = Ref(text=mech.to_text())
+    M = gpu_mech(mech)
+    check_rates(gpu_rates(torch, M, phi, p, ld=157), ref.eval_rates(phi, p), mech, phi, p, "split")
+    base = gpu_jac(torch, M, phi, p, ld=157)
+    check_jac(base, ref.eval_jacobian(phi, p), "split")
+    tried = 0
+    for ts, nt in ((16, 1024), (8, 512), (4, 1024), (2, 512)):
+        try:
+            M.set_variant(1, ts, nt)
+        except Exception:
+            continue
+        tried += 1
+        assert np.array_equal(base, gpu_jac(torch, M, phi, p, ld=157)), (ts, nt)
+    assert tried >= 2
 
 
 # --------------------------------------------------------- paper-shaped configs
