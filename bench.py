@@ -167,7 +167,7 @@ def write_traffic(fetch_dir: str, write_dir: str) -> int:
             return 1
         scale[name] = (COPY_BYTES / 1024.0) / cpy[-1]
         for k, v in rows:
-            m = re.search(r"tile_kernel<(\d+), (\d+), \d+, true>", k)
+            m = re.search(r"tile_kernel<(\d+), (\d+), \d+, true(?:, (?:true|false))?>", k)
             if m:
                 per.setdefault(f"{m.group(1)}x{m.group(2)}", {}).setdefault(name, []).append(v)
     for shape, d in per.items():

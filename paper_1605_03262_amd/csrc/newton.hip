@@ -243,9 +243,9 @@ __global__ void zero_int_kernel(int* p) { *p = 0; }
 
 // ---------------------------------------------------------------- small systems
 // N <= 64: one wavefront per state, lane i holding row i of I - h gamma J in
-// registers (NM = 16, 32 or 64 columns, indexed by compile-time constants
-// only; columns N..NM-1 are zero, so every update runs unguarded over the
-// full width).  A block of SW states shares one workgroup only to read the
+// registers (NM = N rounded up to a multiple of 8 columns, indexed by
+// compile-time constants only; columns N..NM-1 are zero, so every update runs
+// unguarded over the full width).  A block of SW states shares one workgroup only to read the
 // state-fastest Jacobian in coalesced 64-byte runs through LDS; after that
 // every wavefront factors and solves on its own, with no barrier:
 //  * right-looking LU with partial pivoting, rows kept in place (lane i keeps
@@ -602,9 +602,19 @@ hipError_t launch_small_t(int N, int64_t n, int64_t ld, const double* jac, const
 hipError_t launch_small(int N, int64_t n, int64_t ld, const double* jac, const double* h, double gamma,
                         const double* rhs, double* x, int* info, int mode, int max_refine, double rtol,
                         int* list, int* count, hipStream_t st) {
-  if (N <= 16) return launch_small_t<16>(N, n, ld, jac, h, gamma, rhs, x, info, mode, max_refine, rtol, list, count, st);
-  if (N <= 32) return launch_small_t<32>(N, n, ld, jac, h, gamma, rhs, x, info, mode, max_refine, rtol, list, count, st);
-  if (N <= 64) return launch_small_t<64>(N, n, ld, jac, h, gamma, rhs, x, info, mode, max_refine, rtol, list, count, st);
+  // register width: N rounded up to a multiple of 8 (the work per state
+  // grows as NM^2, so the identity border is kept narrow)
+#define PYJAC_SMALL(nm) \
+  if (N <= nm) return launch_small_t<nm>(N, n, ld, jac, h, gamma, rhs, x, info, mode, max_refine, rtol, list, count, st);
+  PYJAC_SMALL(8)
+  PYJAC_SMALL(16)
+  PYJAC_SMALL(24)
+  PYJAC_SMALL(32)
+  PYJAC_SMALL(40)
+  PYJAC_SMALL(48)
+  PYJAC_SMALL(56)
+  PYJAC_SMALL(64)
+#undef PYJAC_SMALL
   return hipErrorInvalidValue;
 }
 
