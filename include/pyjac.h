@@ -74,6 +74,30 @@ pyjac_status pyjac_mech_load(const char* path, int32_t hip_device, pyjac_mech** 
 /* Same as pyjac_mech_load, from a NUL-terminated text buffer. */
 pyjac_status pyjac_mech_load_string(const char* text, int32_t hip_device, pyjac_mech** out);
 
+/* Chemkin-format mechanisms (host only).  Converts Chemkin-II text (ELEMENTS,
+ * SPECIES, REACTIONS and an optional THERMO block) into the token format
+ * above.  `thermo_text` holds the NASA-7 records when they are not in
+ * mech_text (NULL otherwise).  Covered: the reaction classes of Sec. 2.3 as
+ * "+M" third-body, "(+M)"/"(+X)" falloff with LOW (or chemically activated
+ * with HIGH) and TROE/SRI, PLOG and CHEB/TCHEB/PCHEB, REV, efficiencies and
+ * DUPLICATE; units CAL/MOLE (default), KCAL/MOLE, JOULES/MOLE, KJOULES/MOLE,
+ * KELVINS, EVOLTS with MOLES.  A in cm-mol-s is scaled to SI-kmol by
+ * 1e-3^(order-1) (order = molecularity of that coefficient, counting [M]),
+ * pressures from atm to Pa.  Elements without an explicit "/weight/" take
+ * the IUPAC abridged standard atomic weight.
+ * Output: when `out` is NULL only *out_len is set (bytes including the
+ * terminating NUL); otherwise the text is written if out_capacity >= *out_len.
+ * Errors: PYJAC_E_INVALID (NULL mech_text/out_len, buffer too small),
+ * PYJAC_E_PARSE (with the line number in pyjac_last_error), PYJAC_E_UNSUPPORTED
+ * (e.g. MOLECULES units, FORD/RORD, fractional element counts). */
+pyjac_status pyjac_chemkin_to_text(const char* mech_text, const char* thermo_text, char* out,
+                                   size_t out_capacity, size_t* out_len);
+
+/* Reads a Chemkin-format mechanism file (and a separate thermo file, or NULL),
+ * converts it as pyjac_chemkin_to_text does and loads it as pyjac_mech_load. */
+pyjac_status pyjac_mech_load_chemkin(const char* mech_path, const char* thermo_path, int32_t hip_device,
+                                     pyjac_mech** out);
+
 /* Sizes and a 64-bit content hash of the parsed mechanism (any out may be NULL). */
 pyjac_status pyjac_mech_info(const pyjac_mech* mech, int32_t* n_species, int32_t* n_reactions,
                              uint64_t* content_hash);

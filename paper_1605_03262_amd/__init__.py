@@ -10,6 +10,7 @@ from __future__ import annotations
 
 from . import _lib
 from ._lib import PyjacError, load_library  # noqa: F401
+from ._lib import pyjac_chemkin_to_text as chemkin_to_text  # noqa: F401
 
 NEWTON_FP64 = 0
 NEWTON_MIXED = 1
@@ -23,13 +24,23 @@ def _torch():
 class Mechanism:
     """A mechanism whose tables live on one GPU."""
 
-    def __init__(self, path: str | None = None, text: str | None = None, device: int = 0):
-        if (path is None) == (text is None):
-            raise ValueError("give exactly one of path or text")
+    def __init__(self, path: str | None = None, text: str | None = None, device: int = 0,
+                 _handle: int | None = None):
         self.device = device
-        self._h = (_lib.pyjac_mech_load(path, device) if path is not None
-                   else _lib.pyjac_mech_load_string(text, device))
+        if _handle is not None:
+            self._h = _handle
+        else:
+            if (path is None) == (text is None):
+                raise ValueError("give exactly one of path or text")
+            self._h = (_lib.pyjac_mech_load(path, device) if path is not None
+                       else _lib.pyjac_mech_load_string(text, device))
         self.n_species, self.n_reactions, self.content_hash = _lib.pyjac_mech_info(self._h)
+
+    @classmethod
+    def from_chemkin(cls, path: str, thermo: str | None = None, device: int = 0) -> "Mechanism":
+        """Load a Chemkin-format mechanism file (thermo data inside it or in
+        the separate file `thermo`)."""
+        return cls(device=device, _handle=_lib.pyjac_mech_load_chemkin(path, thermo, device))
 
     @property
     def handle(self) -> int:

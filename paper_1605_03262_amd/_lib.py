@@ -19,7 +19,8 @@ STATUS_NAMES = {0: "PYJAC_OK", -1: "PYJAC_E_INVALID", -2: "PYJAC_E_PARSE",
                 -6: "PYJAC_E_IO", -7: "PYJAC_E_UNBALANCED", -8: "PYJAC_E_WORKSPACE"}
 
 # Every symbol include/pyjac.h declares.
-EXPORTED = ("pyjac_mech_load", "pyjac_mech_load_string", "pyjac_mech_info", "pyjac_mech_free",
+EXPORTED = ("pyjac_mech_load", "pyjac_mech_load_string", "pyjac_chemkin_to_text",
+            "pyjac_mech_load_chemkin", "pyjac_mech_info", "pyjac_mech_free",
             "pyjac_eval_rates", "pyjac_eval_jacobian", "pyjac_newton_workspace_bytes",
             "pyjac_newton_factor_solve", "pyjac_mech_set_variant", "pyjac_mech_get_variant",
             "pyjac_mech_autotune", "pyjac_fd_workspace_bytes", "pyjac_eval_jacobian_fd",
@@ -50,6 +51,11 @@ def load_library() -> ctypes.CDLL:
     lib.pyjac_mech_load.restype = st
     lib.pyjac_mech_load_string.argtypes = [ctypes.c_char_p, i32, ctypes.POINTER(vp)]
     lib.pyjac_mech_load_string.restype = st
+    lib.pyjac_chemkin_to_text.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, sz,
+                                          ctypes.POINTER(sz)]
+    lib.pyjac_chemkin_to_text.restype = st
+    lib.pyjac_mech_load_chemkin.argtypes = [ctypes.c_char_p, ctypes.c_char_p, i32, ctypes.POINTER(vp)]
+    lib.pyjac_mech_load_chemkin.restype = st
     lib.pyjac_mech_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                     ctypes.POINTER(ctypes.c_uint64)]
     lib.pyjac_mech_info.restype = st
@@ -114,6 +120,25 @@ def pyjac_mech_load_string(text: str, device: int = 0) -> int:
     h = ctypes.c_void_p()
     check(load_library().pyjac_mech_load_string(text.encode(), device, ctypes.byref(h)),
           "pyjac_mech_load_string")
+    return h.value
+
+
+def pyjac_chemkin_to_text(mech_text: str, thermo_text: str | None = None) -> str:
+    lib = load_library()
+    th = None if thermo_text is None else thermo_text.encode()
+    n = ctypes.c_size_t()
+    check(lib.pyjac_chemkin_to_text(mech_text.encode(), th, None, 0, ctypes.byref(n)), "pyjac_chemkin_to_text")
+    buf = ctypes.create_string_buffer(n.value)
+    check(lib.pyjac_chemkin_to_text(mech_text.encode(), th, buf, n.value, ctypes.byref(n)),
+          "pyjac_chemkin_to_text")
+    return buf.value.decode()
+
+
+def pyjac_mech_load_chemkin(mech_path: str, thermo_path: str | None = None, device: int = 0) -> int:
+    h = ctypes.c_void_p()
+    th = None if thermo_path is None else thermo_path.encode()
+    check(load_library().pyjac_mech_load_chemkin(mech_path.encode(), th, device, ctypes.byref(h)),
+          "pyjac_mech_load_chemkin")
     return h.value
 
 

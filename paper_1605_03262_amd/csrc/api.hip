@@ -221,6 +221,41 @@ pyjac_status pyjac_mech_load(const char* path, int32_t hip_device, pyjac_mech** 
   return pyjac_mech_load_string(ss.str().c_str(), hip_device, out);
 }
 
+pyjac_status pyjac_chemkin_to_text(const char* mech_text, const char* thermo_text, char* out, size_t out_capacity,
+                                   size_t* out_len) {
+  if (!mech_text) return fail(PYJAC_E_INVALID, "mech_text is NULL");
+  if (!out_len) return fail(PYJAC_E_INVALID, "out_len is NULL");
+  std::string th = thermo_text ? thermo_text : "", tokens, msg;
+  const int rc = chemkin_to_tokens(mech_text, thermo_text ? &th : nullptr, tokens, msg);
+  if (rc != PYJAC_OK) return fail(rc, msg);
+  *out_len = tokens.size() + 1;
+  if (!out) return PYJAC_OK;
+  if (out_capacity < tokens.size() + 1) return fail(PYJAC_E_INVALID, "output buffer too small");
+  std::memcpy(out, tokens.c_str(), tokens.size() + 1);
+  return PYJAC_OK;
+}
+
+pyjac_status pyjac_mech_load_chemkin(const char* mech_path, const char* thermo_path, int32_t hip_device,
+                                     pyjac_mech** out) {
+  if (!out) return fail(PYJAC_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!mech_path) return fail(PYJAC_E_INVALID, "mech_path is NULL");
+  auto slurp = [](const char* path, std::string& s) {
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return false;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    s = ss.str();
+    return true;
+  };
+  std::string mech, thermo, tokens, msg;
+  if (!slurp(mech_path, mech)) return fail(PYJAC_E_IO, std::string("cannot read ") + mech_path);
+  if (thermo_path && !slurp(thermo_path, thermo)) return fail(PYJAC_E_IO, std::string("cannot read ") + thermo_path);
+  const int rc = chemkin_to_tokens(mech, thermo_path ? &thermo : nullptr, tokens, msg);
+  if (rc != PYJAC_OK) return fail(rc, msg);
+  return pyjac_mech_load_string(tokens.c_str(), hip_device, out);
+}
+
 pyjac_status pyjac_mech_info(const pyjac_mech* m, int32_t* ns, int32_t* nr, uint64_t* hash) {
   if (!m) return fail(PYJAC_E_INVALID, "mechanism handle is NULL");
   if (ns) *ns = m->host.N;
