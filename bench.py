@@ -124,13 +124,34 @@ def jacobian_only(cfg: int, steps: int) -> int:
         torch.cuda.synchronize()
         newton[name] = {"ms_median": nmed, "fallbacks": int((info[:n] == -2).sum().item())}
     newton["mixed_speedup"] = newton["fp64_lu"]["ms_median"] / newton["fp32_lu_fp64_refine"]["ms_median"]
+    # one SDIRK3 integrator step of the batch: h = c / (gamma ||J||_inf), c log-uniform on [0.1, 10],
+    # 4 simplified-Newton iterations per stage
+    import numpy as np
+    c = np.exp(np.random.default_rng(3262 + 42).uniform(np.log(0.1), np.log(10.0), n))
+    d_hs = torch.from_numpy(c / (NEWTON_GAMMA * rows.max(axis=0))).cuda()
+    del ws
+    out_phi = torch.empty_like(d_phi)
+    sdirk = {"newton_iters": 4, "h": "c / (gamma ||J||_inf), c log-uniform on [0.1, 10]"}
+    for mode, name in ((NEWTON_FP64, "fp64_lu"), (NEWTON_MIXED, "fp32_lu_fp64_refine")):
+        sws = torch.empty((max(_sdirk_ws(M, n, mode), 1),), dtype=torch.uint8, device="cuda")
+        run = lambda: M.sdirk3_step(d_phi, d_p, d_hs, newton_iters=4, mode=mode, out=out_phi,  # noqa: E731
+                                    workspace=sws)
+        smed, _ = time_stream(run, 3, torch)
+        sdirk[name] = {"ms_median": smed, "state_steps_per_s": n / (smed * 1e-3)}
+        del sws
     by = n * (8.0 * N * N + 8.0 * (N + 1))
     print(json.dumps({"workload": CONFIGS[cfg]["name"], "n_states": n, "n_species": N, "newton": newton,
+                      "sdirk3_step": sdirk,
                       "jacobian_ms_median": med, "jacobian_evals_per_s": n / (med * 1e-3),
                       "hbm_frac": by / (med * 1e-3) / 1e9 / HBM_PEAK_GBS,
                       "rhs_ms_median": rmed, "rhs_evals_per_s": n / (rmed * 1e-3),
                       "shape": M.get_variant(1)[:2], "autotune": tuned}), flush=True)
     return 0
+
+
+def _sdirk_ws(M, n, mode):
+    from paper_1605_03262_amd import _lib
+    return _lib.pyjac_sdirk3_workspace_bytes(M.handle, n, n, mode)
 
 
 def _counter_rows(d: str, counter: str):

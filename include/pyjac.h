@@ -145,6 +145,29 @@ pyjac_status pyjac_eval_jacobian_fd(const pyjac_mech* mech, int64_t n_states, in
                                     const double* p, double* jac, void* workspace, size_t workspace_bytes,
                                     void* stream);
 
+/* One implicit integrator step per state (the consumer of J + Newton that
+ * motivates fast Jacobians, Sec. 1): the three-stage, L-stable, stiffly
+ * accurate SDIRK method of order 3 (Alexander, 1977) with diagonal
+ * coefficient gamma = 0.43586652150845899942, a_21 = (1 - gamma)/2,
+ * a_31 = -(6 gamma^2 - 16 gamma + 1)/4, a_32 = (6 gamma^2 - 20 gamma + 5)/4,
+ * a_33 = gamma, y_next = y + z_3.  Stage i solves
+ * z_i = h sum_{j<i} a_ij f(y + z_j) + h gamma f(y + z_i) by simplified Newton
+ * with the matrix I - h gamma J(y) (one Jacobian per step), starting from
+ * z_i = 0, for exactly newton_iters iterations; each iteration evaluates the
+ * RHS and calls pyjac_newton_factor_solve (mode 0 FP64, 1 FP32 LU + FP64
+ * refinement with max_refine 4, rtol 1e-14), which factors again.
+ * phi [N][ld] at constant pressure p [ld] with step h [ld] (seconds) ->
+ * phi_out [N][ld] (may alias phi).  dnorm [3][ld] (or NULL) receives each
+ * stage's last Newton increment max_e |dz_e|, a convergence indicator.
+ * workspace: device memory of pyjac_sdirk3_workspace_bytes(mech, n, ld, mode).
+ * Errors: PYJAC_E_INVALID (NULL arrays, n < 0, ld < n, newton_iters outside
+ * [1, 16], bad mode), PYJAC_E_WORKSPACE, and those of the calls it makes. */
+size_t pyjac_sdirk3_workspace_bytes(const pyjac_mech* mech, int64_t n_states, int64_t ld, int32_t mode);
+pyjac_status pyjac_sdirk3_step(const pyjac_mech* mech, int64_t n_states, int64_t ld, const double* phi,
+                               const double* p, const double* h, int32_t newton_iters, int32_t mode,
+                               double* phi_out, double* dnorm, void* workspace, size_t workspace_bytes,
+                               void* stream);
+
 /* Bytes of device workspace pyjac_newton_factor_solve needs for n_states
  * states in `mode` (0 or 1).  Returns 0 for a bad handle or mode. */
 size_t pyjac_newton_workspace_bytes(const pyjac_mech* mech, int64_t n_states, int32_t mode);

@@ -151,6 +151,28 @@ class Mechanism:
                                        info.data_ptr(), self._ptr(workspace), wsb, self._stream())
         return x, info
 
+    def sdirk3_step(self, phi, p, h, newton_iters: int = 4, mode: int = NEWTON_FP64, out=None,
+                    workspace=None):
+        """One SDIRK3 step per state (constant pressure); returns
+        (phi_next [N, ld], dnorm [3, ld]: each stage's last Newton increment)."""
+        torch = _torch()
+        n, ld = self._check_in(phi, p)
+        N = self.n_species
+        if h.dtype != torch.float64 or not h.is_cuda or h.dim() != 1 or h.shape[0] < n or h.stride(0) != 1:
+            raise ValueError("h must be a contiguous float64 GPU vector covering n_states")
+        if out is None:
+            out = torch.empty((N, ld), dtype=torch.float64, device=phi.device)
+        elif out.shape[0] != N or out.stride(0) != ld or out.stride(1) != 1:
+            raise ValueError("out must be [N, ld] with the same ld as phi")
+        dnorm = torch.empty((3, ld), dtype=torch.float64, device=phi.device)
+        need = _lib.pyjac_sdirk3_workspace_bytes(self._h, n, ld, mode)
+        if workspace is None:
+            workspace = torch.empty((max(need, 1),), dtype=torch.uint8, device=phi.device)
+        wsb = workspace.numel() * workspace.element_size()
+        _lib.pyjac_sdirk3_step(self._h, n, ld, phi.data_ptr(), p.data_ptr(), h.data_ptr(), newton_iters, mode,
+                               out.data_ptr(), dnorm.data_ptr(), workspace.data_ptr(), wsb, self._stream())
+        return out, dnorm
+
     def set_variant(self, which: int, tile_states: int, threads: int) -> None:
         _lib.pyjac_mech_set_variant(self._h, which, tile_states, threads)
 

@@ -24,6 +24,7 @@ EXPORTED = ("pyjac_mech_load", "pyjac_mech_load_string", "pyjac_chemkin_to_text"
             "pyjac_eval_rates", "pyjac_eval_jacobian", "pyjac_newton_workspace_bytes",
             "pyjac_newton_factor_solve", "pyjac_mech_set_variant", "pyjac_mech_get_variant",
             "pyjac_mech_autotune", "pyjac_fd_workspace_bytes", "pyjac_eval_jacobian_fd",
+            "pyjac_sdirk3_workspace_bytes", "pyjac_sdirk3_step",
             "pyjac_status_string", "pyjac_last_error", "pyjac_serve_create", "pyjac_serve_submit",
             "pyjac_serve_wait", "pyjac_serve_stats", "pyjac_serve_destroy")
 
@@ -79,6 +80,10 @@ def load_library() -> ctypes.CDLL:
     lib.pyjac_fd_workspace_bytes.restype = sz
     lib.pyjac_eval_jacobian_fd.argtypes = [vp, i64, i64, vp, vp, vp, vp, sz, vp]
     lib.pyjac_eval_jacobian_fd.restype = st
+    lib.pyjac_sdirk3_workspace_bytes.argtypes = [vp, i64, i64, i32]
+    lib.pyjac_sdirk3_workspace_bytes.restype = sz
+    lib.pyjac_sdirk3_step.argtypes = [vp, i64, i64, vp, vp, vp, i32, i32, vp, vp, vp, sz, vp]
+    lib.pyjac_sdirk3_step.restype = st
     lib.pyjac_mech_autotune.argtypes = [vp, i32, i64, i64, vp, vp, vp, i32, ctypes.POINTER(i32),
                                         ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32), vp]
     lib.pyjac_mech_autotune.restype = st
@@ -238,3 +243,12 @@ def pyjac_serve_stats(server):
 
 def pyjac_serve_destroy(server) -> None:
     check(load_library().pyjac_serve_destroy(server), "pyjac_serve_destroy")
+
+
+def pyjac_sdirk3_workspace_bytes(mech: int, n: int, ld: int, mode: int) -> int:
+    return load_library().pyjac_sdirk3_workspace_bytes(mech, n, ld, mode)
+
+
+def pyjac_sdirk3_step(mech, n, ld, phi, p, h, newton_iters, mode, phi_out, dnorm, ws, wsb, stream):
+    check(load_library().pyjac_sdirk3_step(mech, n, ld, phi, p, h, newton_iters, mode, phi_out, dnorm, ws, wsb,
+                                           stream), "pyjac_sdirk3_step")

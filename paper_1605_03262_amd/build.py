@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpyjac_mi355x.so")
-SOURCES = ["loader.cpp", "chemkin.cpp", "kinetics.hip", "newton.hip", "fd.hip", "serve.cpp", "api.hip"]
+SOURCES = ["loader.cpp", "chemkin.cpp", "kinetics.hip", "newton.hip", "fd.hip", "integ.hip", "serve.cpp", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
