@@ -13,6 +13,7 @@
 
 #include "../../include/pyjac.h"
 #include "tables.hpp"
+#include "chemkin.hpp"
 
 namespace pyjac {
 

@@ -38,6 +38,7 @@
 
 #include "../../include/pyjac.h"
 #include "tables.hpp"
+#include "chemkin.hpp"
 
 namespace pyjac {
 namespace {

@@ -102,10 +102,6 @@ std::vector<int> species_chunk_bounds(const PackedMech& P, int chunk);
 // Parse + validate + pack.  Returns 0 or a PYJAC_E_* code with msg set.
 int build_tables(const std::string& text, PackedMech& out, std::string& msg);
 
-// Chemkin-format mechanism (and optional separate thermo text) -> the token
-// format build_tables reads.  Returns 0 or a PYJAC_E_* code with msg set.
-int chemkin_to_tokens(const std::string& mech, const std::string* thermo, std::string& out, std::string& msg);
-
 // Device view (all pointers into one device allocation).
 struct MechDev {
   int N, NR, NG;
