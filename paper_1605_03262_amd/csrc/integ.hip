@@ -6,7 +6,8 @@
 // Stage i solves z_i = h sum_{j<i} a_ij F_j + h gamma f(y + z_i), F_j =
 // f(y + z_j), by simplified Newton with the matrix I - h gamma J(y) from
 // z_i = 0 for a fixed number of iterations; y_next = y + z_3.  The RHS, the
-// Jacobian and the Newton solves are the library's own kernels; the kernels
+// Jacobian and the Newton solves are the library's own kernels (the matrix is
+// factored once per step where the Newton path keeps its factor); the kernels
 // here only combine per-state vectors, element-major with the state fastest
 // like every other array (coalesced, HBM-bound, no reductions across states).
 #include <hip/hip_runtime.h>
@@ -157,8 +158,9 @@ pyjac_status pyjac_sdirk3_step(const pyjac_mech* m, int64_t n, int64_t ld, const
       if (rc != PYJAC_OK) return rc;
       if (sdirk_stage_rhs(N, n, ld, h, a1, F1, a2, F2, fz, z, rhs, st) != hipSuccess)
         return fail(PYJAC_E_DEVICE, "launch failed");
-      rc = pyjac_newton_factor_solve(m, n, ld, J, h, kG, rhs, d, mode, 4, 1e-14, info, nws, nwsb,
-                                     stream);
+      // I - h gamma J(y) is the same for every solve of the step: factored once
+      const int32_t nmode = (i == 0 && it == 0) ? mode : (mode | PYJAC_NEWTON_REUSE_FACTOR);
+      rc = pyjac_newton_factor_solve(m, n, ld, J, h, kG, rhs, d, nmode, 4, 1e-14, info, nws, nwsb, stream);
       if (rc != PYJAC_OK) return rc;
       // the last update of the last stage writes the result (y + z_3)
       double* dst = (i == 2 && it == newton_iters - 1) ? phi_out : Y;

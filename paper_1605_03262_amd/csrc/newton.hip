@@ -737,6 +737,13 @@ __global__ void init_status_kernel(int64_t n, int* __restrict__ status, double* 
     for (int i = 0; i < N; ++i) xs[(int64_t)i * n + s] = 0.0;
 }
 
+// dst[s] = src[s]: keeps the status left by a factorization (singular
+// states) for later calls that reuse the factor
+__global__ void copy_status_kernel(int64_t n, const int* __restrict__ src, int* __restrict__ dst) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) dst[s] = src[s];
+}
+
 __global__ void copy_rhs_kernel(int N, int64_t n, int64_t ld, const double* __restrict__ rhs, double* __restrict__ rbuf) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
@@ -774,7 +781,8 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 size_t small_ws_bytes(int64_t n, int mode) { return mode == 1 ? align256((size_t)n * sizeof(int)) + 256 : 0; }
 
 struct WsLayout {
-  size_t a32 = 0, a64 = 0, piv = 0, status = 0, fbstatus = 0, xs = 0, rbuf = 0, list = 0, count = 0, total = 0;
+  size_t a32 = 0, a64 = 0, piv = 0, piv64 = 0, sing = 0, status = 0, fbstatus = 0, xs = 0, rbuf = 0, list = 0,
+         count = 0, total = 0;
 };
 
 WsLayout ws_layout(int N, int64_t n, int mode) {
@@ -785,6 +793,8 @@ WsLayout ws_layout(int N, int64_t n, int mode) {
   if (mode == 1) L.a32 = take((size_t)n * NN * sizeof(float));
   L.a64 = take((size_t)n * NN * sizeof(double));
   L.piv = take((size_t)n * N * sizeof(int));
+  L.piv64 = mode == 1 ? take((size_t)n * N * sizeof(int)) : L.piv;   // the FP64 fallback's own pivots
+  L.sing = take((size_t)n * sizeof(int));                              // status after factorization
   L.status = take((size_t)n * sizeof(int));
   L.fbstatus = take((size_t)n * sizeof(int));
   if (mode == 1) {
@@ -802,13 +812,18 @@ size_t lu_lds(int N, size_t elem) { return ((size_t)N * (NB + 1) + (size_t)NB * 
 template <typename T>
 hipError_t run_direct(int N, int64_t n, int64_t ld, const double* jac, const double* h, double gamma,
                       const double* rhs, double* x, T* A, int* piv, const int* list, const int* count, int* status,
-                      hipStream_t st) {
-  dim3 fg((unsigned)((n + 15) / 16), (unsigned)(((int64_t)N * N + 63) / 64));
-  hipLaunchKernelGGL(form_kernel<T>, fg, dim3(256), 0, st, N, n, ld, jac, h, gamma, A, list, count, status);
-  const size_t lds = lu_lds(N, sizeof(T));
-  hipError_t e = hipFuncSetAttribute((const void*)lu_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(lu_kernel<T>, dim3((unsigned)n), dim3(LU_THREADS), lds, st, N, n, A, piv, list, count, status, -1);
+                      hipStream_t st, bool factor = true, int* save_status = nullptr) {
+  if (factor) {
+    dim3 fg((unsigned)((n + 15) / 16), (unsigned)(((int64_t)N * N + 63) / 64));
+    hipLaunchKernelGGL(form_kernel<T>, fg, dim3(256), 0, st, N, n, ld, jac, h, gamma, A, list, count, status);
+    const size_t lds = lu_lds(N, sizeof(T));
+    hipError_t e = hipFuncSetAttribute((const void*)lu_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(lu_kernel<T>, dim3((unsigned)n), dim3(LU_THREADS), lds, st, N, n, A, piv, list, count, status, -1);
+    if (save_status)
+      hipLaunchKernelGGL(copy_status_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
+                         (const int*)status, save_status);
+  }
   hipLaunchKernelGGL((solve_kernel<T, false>), dim3((unsigned)((n + 3) / 4)), dim3(256), 4 * N * sizeof(T), st, N, n, ld,
                      (const T*)A, (const int*)piv, rhs, (const double*)nullptr, (double*)nullptr, x, list, count, status, 0,
                      0.0);
@@ -823,6 +838,7 @@ using namespace pyjac;
 extern "C" {
 
 size_t pyjac_newton_workspace_bytes(const pyjac_mech* m, int64_t n, int32_t mode) {
+  mode &= ~PYJAC_NEWTON_REUSE_FACTOR;
   if (!m || n < 0 || (mode != 0 && mode != 1)) return 0;
   if (mech_species(m) <= kSmallMax) return small_ws_bytes(n, mode);
   return ws_layout(mech_species(m), n, mode).total;
@@ -834,7 +850,9 @@ pyjac_status pyjac_newton_factor_solve(const pyjac_mech* m, int64_t n, int64_t l
                                        void* stream) {
   if (!m) return fail(PYJAC_E_INVALID, "mechanism handle is NULL");
   if (n < 0 || ld < n) return fail(PYJAC_E_INVALID, "bad n_states / ld");
-  if (mode != 0 && mode != 1) return fail(PYJAC_E_INVALID, "mode must be 0 or 1");
+  const bool reuse = (mode & PYJAC_NEWTON_REUSE_FACTOR) != 0;
+  mode &= ~PYJAC_NEWTON_REUSE_FACTOR;
+  if (mode != 0 && mode != 1) return fail(PYJAC_E_INVALID, "mode must be 0 or 1 (optionally | PYJAC_NEWTON_REUSE_FACTOR)");
   if (mode == 1 && (max_refine < 1 || max_refine > 100 || !(rtol > 0))) return fail(PYJAC_E_INVALID, "bad max_refine / rtol");
   if (n == 0) return PYJAC_OK;
   if (!jac || !h || !rhs || !x || !info) return fail(PYJAC_E_INVALID, "NULL array argument");
@@ -865,12 +883,20 @@ pyjac_status pyjac_newton_factor_solve(const pyjac_mech* m, int64_t n, int64_t l
   int* status = reinterpret_cast<int*>(w + L.status);
   int* fbs = reinterpret_cast<int*>(w + L.fbstatus);
   int* piv = reinterpret_cast<int*>(w + L.piv);
+  int* piv64 = reinterpret_cast<int*>(w + L.piv64);
+  int* sing = reinterpret_cast<int*>(w + L.sing);
   double* A64 = reinterpret_cast<double*>(w + L.a64);
   const unsigned g1 = (unsigned)((n + 255) / 256);
   hipError_t e;
+  // With PYJAC_NEWTON_REUSE_FACTOR the factor (and the status it left) is the
+  // one a previous call with the same J, h, gamma, n, ld and mode stored in
+  // this workspace; form and factorization are skipped.
   if (mode == 0) {
-    hipLaunchKernelGGL(init_status_kernel, dim3(g1), dim3(256), 0, st, n, status, (double*)nullptr, N);
-    e = run_direct<double>(N, n, ld, jac, h, gamma, rhs, x, A64, piv, nullptr, nullptr, status, st);
+    if (reuse)
+      hipLaunchKernelGGL(copy_status_kernel, dim3(g1), dim3(256), 0, st, n, (const int*)sing, status);
+    else
+      hipLaunchKernelGGL(init_status_kernel, dim3(g1), dim3(256), 0, st, n, status, (double*)nullptr, N);
+    e = run_direct<double>(N, n, ld, jac, h, gamma, rhs, x, A64, piv, nullptr, nullptr, status, st, !reuse, sing);
     if (e == hipSuccess) {
       hipLaunchKernelGGL(finish_kernel, dim3(g1), dim3(256), 0, st, N, n, ld, (const int*)status, (const double*)nullptr,
                          x, info, (const int*)nullptr, 0);
@@ -883,15 +909,19 @@ pyjac_status pyjac_newton_factor_solve(const pyjac_mech* m, int64_t n, int64_t l
     int* list = reinterpret_cast<int*>(w + L.list);
     int* count = reinterpret_cast<int*>(w + L.count);
     hipLaunchKernelGGL(init_status_kernel, dim3(g1), dim3(256), 0, st, n, status, xs, N);
+    if (reuse) hipLaunchKernelGGL(copy_status_kernel, dim3(g1), dim3(256), 0, st, n, (const int*)sing, status);
     hipLaunchKernelGGL(copy_rhs_kernel, dim3(g1), dim3(256), 0, st, N, n, ld, rhs, rbuf);
-    dim3 fg((unsigned)((n + 15) / 16), (unsigned)(((int64_t)N * N + 63) / 64));
-    hipLaunchKernelGGL(form_kernel<float>, fg, dim3(256), 0, st, N, n, ld, jac, h, gamma, A32, (const int*)nullptr,
-                       (const int*)nullptr, status);
-    const size_t lds = lu_lds(N, sizeof(float));
-    e = hipFuncSetAttribute((const void*)lu_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return fail(PYJAC_E_DEVICE, hipGetErrorString(e));
-    hipLaunchKernelGGL(lu_kernel<float>, dim3((unsigned)n), dim3(LU_THREADS), lds, st, N, n, A32, piv,
-                       (const int*)nullptr, (const int*)nullptr, status, ST_SING32);
+    if (!reuse) {
+      dim3 fg((unsigned)((n + 15) / 16), (unsigned)(((int64_t)N * N + 63) / 64));
+      hipLaunchKernelGGL(form_kernel<float>, fg, dim3(256), 0, st, N, n, ld, jac, h, gamma, A32, (const int*)nullptr,
+                         (const int*)nullptr, status);
+      const size_t lds = lu_lds(N, sizeof(float));
+      e = hipFuncSetAttribute((const void*)lu_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return fail(PYJAC_E_DEVICE, hipGetErrorString(e));
+      hipLaunchKernelGGL(lu_kernel<float>, dim3((unsigned)n), dim3(LU_THREADS), lds, st, N, n, A32, piv,
+                         (const int*)nullptr, (const int*)nullptr, status, ST_SING32);
+      hipLaunchKernelGGL(copy_status_kernel, dim3(g1), dim3(256), 0, st, n, (const int*)status, sing);
+    }
     const unsigned gs = (unsigned)((n + 3) / 4);
     for (int sweep = 0; sweep <= max_refine; ++sweep) {
       if (sweep > 0)
@@ -906,7 +936,8 @@ pyjac_status pyjac_newton_factor_solve(const pyjac_mech* m, int64_t n, int64_t l
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, count);
     hipLaunchKernelGGL(compact_kernel, dim3(g1), dim3(256), 0, st, n, (const int*)status, list, count);
     hipLaunchKernelGGL(init_status_kernel, dim3(g1), dim3(256), 0, st, n, fbs, (double*)nullptr, N);
-    e = run_direct<double>(N, n, ld, jac, h, gamma, rhs, x, A64, piv, list, count, fbs, st);
+    // (always factored: which states fall back depends on the right-hand side)
+    e = run_direct<double>(N, n, ld, jac, h, gamma, rhs, x, A64, piv64, list, count, fbs, st);
     if (e == hipSuccess) {
       hipLaunchKernelGGL(finish_kernel, dim3(g1), dim3(256), 0, st, N, n, ld, (const int*)status, (const double*)xs, x,
                          info, (const int*)fbs, 1);

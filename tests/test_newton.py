@@ -165,3 +165,33 @@ def test_newton_full_size_backward_error(mode):
         r = b[:, s].astype(np.longdouble) - A.astype(np.longdouble) @ xs[:, c].astype(np.longdouble)
         bound = 4 * N * U * (np.abs(A).sum(axis=1).max() * np.abs(xs[:, c]).max() + np.abs(b[:, s]).max())
         assert float(np.abs(r).max()) <= bound, (s, float(np.abs(r).max()), bound)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("cfg,n", [(2, 64), (1, 64)])
+def test_reused_factor_equals_fresh_solve(cfg, n):
+    """A solve with PYJAC_NEWTON_REUSE_FACTOR after a solve of the same
+    matrix equals a fresh solve bitwise (blocked path: the factor kept in the
+    workspace; register path: the flag is accepted and the system factored)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_03262_amd import NEWTON_FP64, NEWTON_MIXED, NEWTON_REUSE_FACTOR, Mechanism
+    from synth import NEWTON_GAMMA, conditioned_steps, draw_newton_inputs
+    mech = config_mechanism(cfg)
+    N = mech.n_species
+    phi, p = config_states(cfg, n)
+    M = Mechanism(text=mech.to_text())
+    J = M.eval_jacobian(torch.from_numpy(phi).cuda(), torch.from_numpy(p).cuda())
+    rows = torch.abs(J.view(N, N, n)).sum(dim=1).cpu().numpy()
+    h = torch.from_numpy(conditioned_steps(7, rows)).cuda()
+    b1 = torch.from_numpy(draw_newton_inputs(8, N, n)[1]).cuda()
+    b2 = torch.from_numpy(draw_newton_inputs(9, N, n)[1]).cuda()
+    for mode in (NEWTON_FP64, NEWTON_MIXED):
+        ws = torch.empty((max(M.newton_workspace_bytes(n, mode), 1),), dtype=torch.uint8, device="cuda")
+        M.newton_solve(J, h, b1, NEWTON_GAMMA, mode=mode, workspace=ws)
+        xr, ir = M.newton_solve(J, h, b2, NEWTON_GAMMA, mode=mode | NEWTON_REUSE_FACTOR, workspace=ws)
+        xf, i_f = M.newton_solve(J, h, b2, NEWTON_GAMMA, mode=mode)
+        torch.cuda.synchronize()
+        assert torch.equal(xr, xf), mode
+        assert torch.equal(ir[:n], i_f[:n]), mode
