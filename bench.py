@@ -86,8 +86,9 @@ def pmc_pass(n_launch: int = 3) -> int:
     return 0
 
 
-PMC_COMMAND = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 120 rocprofv3 --pmc {c} -d $R/gpurun_out/{d} "
-               "-o {o} --output-format csv -- python3 $R/bench.py --pmc-pass   (R = repository root)")
+PMC_COMMAND = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 120 rocprofv3 --pmc {c} -d $OUT/{d} "
+               "-o {o} --output-format csv -- python3 $R/bench.py --pmc-pass   "
+               "(R = repository root, OUT = output folder)")
 
 
 def jacobian_only(cfg: int, steps: int) -> int:
