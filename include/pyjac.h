@@ -156,8 +156,8 @@ pyjac_status pyjac_eval_jacobian_fd(const pyjac_mech* mech, int64_t n_states, in
  * z_i = 0, for exactly newton_iters iterations; each iteration evaluates the
  * RHS and calls pyjac_newton_factor_solve (mode 0 FP64, 1 FP32 LU + FP64
  * refinement with max_refine 4, rtol 1e-14); every solve after the step's
- * first passes PYJAC_NEWTON_REUSE_FACTOR, so for N > 64 the matrix is
- * factored once per step (N <= 64: once per solve, in registers).
+ * first passes PYJAC_NEWTON_REUSE_FACTOR (the first, KEEP), so in mode 0
+ * the matrix is factored once per step (mode 1 with N <= 64: once per solve).
  * phi [N][ld] at constant pressure p [ld] with step h [ld] (seconds) ->
  * phi_out [N][ld] (may alias phi).  dnorm [3][ld] (or NULL) receives each
  * stage's last Newton increment max_e |dz_e|, a convergence indicator.
@@ -171,7 +171,8 @@ pyjac_status pyjac_sdirk3_step(const pyjac_mech* mech, int64_t n_states, int64_t
                                void* stream);
 
 /* Bytes of device workspace pyjac_newton_factor_solve needs for n_states
- * states in `mode` (0 or 1; PYJAC_NEWTON_REUSE_FACTOR is ignored here).
+ * states in `mode` (0 or 1; with PYJAC_NEWTON_KEEP_FACTOR including the kept
+ * factor's storage; PYJAC_NEWTON_REUSE_FACTOR is ignored here).
  * Returns 0 for a bad handle or mode. */
 size_t pyjac_newton_workspace_bytes(const pyjac_mech* mech, int64_t n_states, int32_t mode);
 
@@ -196,11 +197,19 @@ size_t pyjac_newton_workspace_bytes(const pyjac_mech* mech, int64_t n_states, in
  * workspace, skipping the formation and factorization of A (for the several
  * solves of one implicit step).  The caller guarantees that nothing else
  * used the workspace in between and orders the calls on one stream.  Only
- * the blocked path (N > 64) keeps its factor in the workspace; for N <= 64
- * the factor lives in registers, so the flag is accepted and the system is
- * factored again.  States that fall back to FP64 in mode 1 are always
+ * the blocked path (N > 64) keeps its factor in the workspace on its own;
+ * for N <= 64 (mode 0) the factoring call must have passed
+ * PYJAC_NEWTON_KEEP_FACTOR (mode 1: the flag is accepted and the system is
+ * factored again).  States that fall back to FP64 in mode 1 are always
  * factored again.  Errors: PYJAC_E_INVALID, PYJAC_E_WORKSPACE, PYJAC_E_DEVICE. */
 #define PYJAC_NEWTON_REUSE_FACTOR 16
+/* mode | PYJAC_NEWTON_KEEP_FACTOR: keep the FP64 factor of the register
+ * path (N <= 64, mode 0) in the workspace for later REUSE calls; the
+ * workspace must then hold pyjac_newton_workspace_bytes(mech, n, mode |
+ * PYJAC_NEWTON_KEEP_FACTOR) bytes (N^2-sized per state).  The blocked path
+ * always keeps its factor; on the register path in mode 1 the flag is
+ * accepted and the system factored on every call. */
+#define PYJAC_NEWTON_KEEP_FACTOR 32
 pyjac_status pyjac_newton_factor_solve(const pyjac_mech* mech, int64_t n_states, int64_t ld,
                                        const double* jac, const double* h, double gamma,
                                        const double* rhs, double* x, int32_t mode,

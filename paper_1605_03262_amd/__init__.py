@@ -15,6 +15,7 @@ from ._lib import pyjac_chemkin_to_text as chemkin_to_text  # noqa: F401
 NEWTON_FP64 = 0
 NEWTON_MIXED = 1
 NEWTON_REUSE_FACTOR = 16     # or-ed into the mode: solve with the factor kept in the workspace
+NEWTON_KEEP_FACTOR = 32      # or-ed into the mode: keep the register path's FP64 factor there
 
 
 def _torch():

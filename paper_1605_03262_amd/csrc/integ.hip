@@ -111,7 +111,7 @@ SdirkLayout sdirk_layout(const pyjac_mech* m, int64_t n, int64_t ld, int32_t mod
   L.vec = align256((size_t)N * N * ld * sizeof(double));
   L.info = L.vec + 7 * align256((size_t)N * ld * sizeof(double));
   L.nws = L.info + align256((size_t)ld * sizeof(int32_t));
-  L.total = L.nws + align256(pyjac_newton_workspace_bytes(m, n, mode));
+  L.total = L.nws + align256(pyjac_newton_workspace_bytes(m, n, mode | PYJAC_NEWTON_KEEP_FACTOR));
   return L;
 }
 
@@ -159,7 +159,7 @@ pyjac_status pyjac_sdirk3_step(const pyjac_mech* m, int64_t n, int64_t ld, const
       if (sdirk_stage_rhs(N, n, ld, h, a1, F1, a2, F2, fz, z, rhs, st) != hipSuccess)
         return fail(PYJAC_E_DEVICE, "launch failed");
       // I - h gamma J(y) is the same for every solve of the step: factored once
-      const int32_t nmode = (i == 0 && it == 0) ? mode : (mode | PYJAC_NEWTON_REUSE_FACTOR);
+      const int32_t nmode = mode | ((i == 0 && it == 0) ? PYJAC_NEWTON_KEEP_FACTOR : PYJAC_NEWTON_REUSE_FACTOR);
       rc = pyjac_newton_factor_solve(m, n, ld, J, h, kG, rhs, d, nmode, 4, 1e-14, info, nws, nwsb, stream);
       if (rc != PYJAC_OK) return rc;
       // the last update of the last stage writes the result (y + z_3)

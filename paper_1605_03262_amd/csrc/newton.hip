@@ -450,7 +450,13 @@ __global__ __launch_bounds__(SW * 64, 2) void small_fp64_kernel(int N, int64_t n
                                                                 const double* __restrict__ rhs,
                                                                 double* __restrict__ x, int* __restrict__ info,
                                                                 const int* __restrict__ list,
-                                                                const int* __restrict__ count) {
+                                                                const int* __restrict__ count,
+                                                                double* __restrict__ fstore = nullptr,
+                                                                int* __restrict__ sstore = nullptr,
+                                                                int* __restrict__ fstat = nullptr, int fmode = 0) {
+  // fmode 1: also store the factor (lane i's row, its pivot step) and the
+  // state's factorization status; fmode 2: take them from a previous fmode-1
+  // launch instead of loading J and factoring (uniform over the launch).
   // wave-private buffers first, so their offsets fit the LDS instructions'
   // immediate offset fields; the staging area follows
   extern __shared__ double slds[];
@@ -470,17 +476,45 @@ __global__ __launch_bounds__(SW * 64, 2) void small_fp64_kernel(int N, int64_t n
   if (lane < NM) xv[lane] = 0.0;
   const double hg = live ? h[s] * gamma : 0.0;
   double a64[NM];
-  const bool fin = __all(small_load<NM, SW>(a64, N, ld, jac, sst, hg, lane, wv, stage));
   const double b = (live && lane < N) ? rhs[(int64_t)lane * ld + s] : 0.0;
-  int status = fin ? 0 : -3;
   bool solved = false;
-  if (live && fin) {
-    int stp;
-    if (small_lu<NM, double>(a64, lane, stp)) {
+  int status;
+  if (fmode == 2) {
+    // stored factor: lanes NM..63 hold nothing and never pivot
+    sfor<0, NM>([&](auto j) { a64[j] = 0.0; });
+    int stp = NM;
+    status = live ? fstat[s] : 0;
+    if (live && status == 0) {
+      if (lane < NM) {
+        const double* fr = fstore + ((int64_t)s * NM + lane) * NM;
+        sfor<0, NM>([&](auto j) { a64[j] = fr[j]; });
+        stp = sstore[(int64_t)s * NM + lane];
+      }
       small_solve<NM, double>(a64, stp, b, xv);
       solved = true;
-      status = __all(lane >= N || isfinite(xv[lane])) ? (list ? -2 : 0) : -1;
-    } else status = -1;
+      status = __all(lane >= N || isfinite(xv[lane])) ? 0 : -1;
+    }
+  } else {
+    const bool fin = __all(small_load<NM, SW>(a64, N, ld, jac, sst, hg, lane, wv, stage));
+    status = fin ? 0 : -3;
+    int fst = status;
+    if (live && fin) {
+      int stp;
+      if (small_lu<NM, double>(a64, lane, stp)) {
+        if (fmode == 1 && lane < NM) {
+          double* fr = fstore + ((int64_t)s * NM + lane) * NM;
+          sfor<0, NM>([&](auto j) { fr[j] = a64[j]; });
+          sstore[(int64_t)s * NM + lane] = stp;
+        }
+        small_solve<NM, double>(a64, stp, b, xv);
+        solved = true;
+        status = __all(lane >= N || isfinite(xv[lane])) ? (list ? -2 : 0) : -1;
+      } else {
+        status = -1;
+        fst = -1;
+      }
+    }
+    if (fmode == 1 && live && lane == 0) fstat[s] = fst;
   }
   if (live && lane == 0) info[s] = status;
   if (solved && lane < N) x[(int64_t)lane * ld + s] = xv[lane];
@@ -573,15 +607,23 @@ size_t small_lds(int N, int NM, int SW) { return ((size_t)SRB * N * SW + 3 * (si
 template <int NM>
 hipError_t launch_small_t(int N, int64_t n, int64_t ld, const double* jac, const double* h, double gamma,
                           const double* rhs, double* x, int* info, int mode, int max_refine, double rtol,
-                          int* list, int* count, hipStream_t st) {
+                          int* list, int* count, hipStream_t st, void* fws, int fmode) {
   const size_t lds = small_lds(N, NM, SW8);
   const unsigned grid = (unsigned)((n + SW8 - 1) / SW8);
   auto k64 = small_fp64_kernel<NM>;
   hipError_t e = hipFuncSetAttribute((const void*)k64, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   if (mode == 0) {
+    // kept factor: [state][row][NM] doubles, then [state][NM] pivot steps, then [state] status
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    char* fw = static_cast<char*>(fws);
+    double* fstore = fws ? reinterpret_cast<double*>(fw) : nullptr;
+    int* sstore = fws ? reinterpret_cast<int*>(fw + al((size_t)n * NM * NM * sizeof(double))) : nullptr;
+    int* fstat = fws ? reinterpret_cast<int*>(fw + al((size_t)n * NM * NM * sizeof(double)) +
+                                              al((size_t)n * NM * sizeof(int)))
+                     : nullptr;
     hipLaunchKernelGGL(k64, dim3(grid), dim3(SW8 * 64), lds, st, N, n, ld, jac, h, gamma, rhs, x, info,
-                       (const int*)nullptr, (const int*)nullptr);
+                       (const int*)nullptr, (const int*)nullptr, fstore, sstore, fstat, fws ? fmode : 0);
     return hipGetLastError();
   }
   constexpr int SWM = SW8;
@@ -595,17 +637,17 @@ hipError_t launch_small_t(int N, int64_t n, int64_t ld, const double* jac, const
   hipLaunchKernelGGL(small_compact_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
                      (const int*)info, list, count);
   hipLaunchKernelGGL(k64, dim3(grid), dim3(SW8 * 64), lds, st, N, n, ld, jac, h, gamma, rhs, x, info,
-                     (const int*)list, (const int*)count);
+                     (const int*)list, (const int*)count, (double*)nullptr, (int*)nullptr, (int*)nullptr, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_small(int N, int64_t n, int64_t ld, const double* jac, const double* h, double gamma,
                         const double* rhs, double* x, int* info, int mode, int max_refine, double rtol,
-                        int* list, int* count, hipStream_t st) {
+                        int* list, int* count, hipStream_t st, void* fws, int fmode) {
   // register width: N rounded up to a multiple of 8 (the work per state
   // grows as NM^2, so the identity border is kept narrow)
 #define PYJAC_SMALL(nm) \
-  if (N <= nm) return launch_small_t<nm>(N, n, ld, jac, h, gamma, rhs, x, info, mode, max_refine, rtol, list, count, st);
+  if (N <= nm) return launch_small_t<nm>(N, n, ld, jac, h, gamma, rhs, x, info, mode, max_refine, rtol, list, count, st, fws, fmode);
   PYJAC_SMALL(8)
   PYJAC_SMALL(16)
   PYJAC_SMALL(24)
@@ -780,6 +822,14 @@ __global__ void finish_kernel(int N, int64_t n, int64_t ld, const int* __restric
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 size_t small_ws_bytes(int64_t n, int mode) { return mode == 1 ? align256((size_t)n * sizeof(int)) + 256 : 0; }
 
+// FP64 factor kept for reuse on the register path (mode 0): rows of NM
+// doubles, NM pivot steps and one status per state
+size_t small_keep_bytes(int N, int64_t n) {
+  const size_t NM = (size_t)((N + 7) / 8) * 8;
+  return align256((size_t)n * NM * NM * sizeof(double)) + align256((size_t)n * NM * sizeof(int)) +
+         align256((size_t)n * sizeof(int));
+}
+
 struct WsLayout {
   size_t a32 = 0, a64 = 0, piv = 0, piv64 = 0, sing = 0, status = 0, fbstatus = 0, xs = 0, rbuf = 0, list = 0,
          count = 0, total = 0;
@@ -838,9 +888,11 @@ using namespace pyjac;
 extern "C" {
 
 size_t pyjac_newton_workspace_bytes(const pyjac_mech* m, int64_t n, int32_t mode) {
-  mode &= ~PYJAC_NEWTON_REUSE_FACTOR;
+  const bool keep = (mode & PYJAC_NEWTON_KEEP_FACTOR) != 0;
+  mode &= ~(PYJAC_NEWTON_REUSE_FACTOR | PYJAC_NEWTON_KEEP_FACTOR);
   if (!m || n < 0 || (mode != 0 && mode != 1)) return 0;
-  if (mech_species(m) <= kSmallMax) return small_ws_bytes(n, mode);
+  if (mech_species(m) <= kSmallMax)
+    return (keep && mode == 0) ? small_keep_bytes(mech_species(m), n) : small_ws_bytes(n, mode);
   return ws_layout(mech_species(m), n, mode).total;
 }
 
@@ -851,7 +903,8 @@ pyjac_status pyjac_newton_factor_solve(const pyjac_mech* m, int64_t n, int64_t l
   if (!m) return fail(PYJAC_E_INVALID, "mechanism handle is NULL");
   if (n < 0 || ld < n) return fail(PYJAC_E_INVALID, "bad n_states / ld");
   const bool reuse = (mode & PYJAC_NEWTON_REUSE_FACTOR) != 0;
-  mode &= ~PYJAC_NEWTON_REUSE_FACTOR;
+  const bool keep = (mode & PYJAC_NEWTON_KEEP_FACTOR) != 0;
+  mode &= ~(PYJAC_NEWTON_REUSE_FACTOR | PYJAC_NEWTON_KEEP_FACTOR);
   if (mode != 0 && mode != 1) return fail(PYJAC_E_INVALID, "mode must be 0 or 1 (optionally | PYJAC_NEWTON_REUSE_FACTOR)");
   if (mode == 1 && (max_refine < 1 || max_refine > 100 || !(rtol > 0))) return fail(PYJAC_E_INVALID, "bad max_refine / rtol");
   if (n == 0) return PYJAC_OK;
@@ -866,13 +919,17 @@ pyjac_status pyjac_newton_factor_solve(const pyjac_mech* m, int64_t n, int64_t l
   const int N = mech_species(m);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (N <= kSmallMax) {     // register-resident path; mixed mode needs only the fallback list
-    const size_t need = small_ws_bytes(n, mode);
+    // FP64 with a kept factor: the workspace holds it; mixed mode factors every call
+    const bool kept = mode == 0 && (keep || reuse);
+    const size_t need = kept ? small_keep_bytes(N, n) : small_ws_bytes(n, mode);
     if (need && (!workspace || workspace_bytes < need))
       return fail(PYJAC_E_WORKSPACE, "workspace smaller than pyjac_newton_workspace_bytes");
-    int* list = need ? reinterpret_cast<int*>(workspace) : nullptr;
-    int* count = need ? reinterpret_cast<int*>(static_cast<char*>(workspace) + align256((size_t)n * sizeof(int)))
-                      : nullptr;
-    const hipError_t e = launch_small(N, n, ld, jac, h, gamma, rhs, x, info, mode, max_refine, rtol, list, count, st);
+    int* list = (need && !kept) ? reinterpret_cast<int*>(workspace) : nullptr;
+    int* count = (need && !kept)
+                     ? reinterpret_cast<int*>(static_cast<char*>(workspace) + align256((size_t)n * sizeof(int)))
+                     : nullptr;
+    const hipError_t e = launch_small(N, n, ld, jac, h, gamma, rhs, x, info, mode, max_refine, rtol, list, count, st,
+                                      kept ? workspace : nullptr, reuse ? 2 : 1);
     if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("newton launch failed: ") + hipGetErrorString(e));
     return PYJAC_OK;
   }

@@ -168,15 +168,16 @@ def test_newton_full_size_backward_error(mode):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("cfg,n", [(2, 64), (1, 64)])
+@pytest.mark.parametrize("cfg,n", [(2, 64), (1, 64), (0, 37)])
 def test_reused_factor_equals_fresh_solve(cfg, n):
-    """A solve with PYJAC_NEWTON_REUSE_FACTOR after a solve of the same
-    matrix equals a fresh solve bitwise (blocked path: the factor kept in the
-    workspace; register path: the flag is accepted and the system factored)."""
+    """Solves with PYJAC_NEWTON_REUSE_FACTOR after a PYJAC_NEWTON_KEEP_FACTOR
+    solve of the same matrix equal fresh solves bitwise (blocked path and
+    register-path FP64: the factor kept in the workspace; register-path
+    mixed mode: the flags are accepted and the system factored)."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    from paper_1605_03262_amd import NEWTON_FP64, NEWTON_MIXED, NEWTON_REUSE_FACTOR, Mechanism
+    from paper_1605_03262_amd import NEWTON_FP64, NEWTON_KEEP_FACTOR, NEWTON_MIXED, NEWTON_REUSE_FACTOR, Mechanism
     from synth import NEWTON_GAMMA, conditioned_steps, draw_newton_inputs
     mech = config_mechanism(cfg)
     N = mech.n_species
@@ -188,10 +189,14 @@ def test_reused_factor_equals_fresh_solve(cfg, n):
     b1 = torch.from_numpy(draw_newton_inputs(8, N, n)[1]).cuda()
     b2 = torch.from_numpy(draw_newton_inputs(9, N, n)[1]).cuda()
     for mode in (NEWTON_FP64, NEWTON_MIXED):
-        ws = torch.empty((max(M.newton_workspace_bytes(n, mode), 1),), dtype=torch.uint8, device="cuda")
-        M.newton_solve(J, h, b1, NEWTON_GAMMA, mode=mode, workspace=ws)
-        xr, ir = M.newton_solve(J, h, b2, NEWTON_GAMMA, mode=mode | NEWTON_REUSE_FACTOR, workspace=ws)
-        xf, i_f = M.newton_solve(J, h, b2, NEWTON_GAMMA, mode=mode)
-        torch.cuda.synchronize()
-        assert torch.equal(xr, xf), mode
-        assert torch.equal(ir[:n], i_f[:n]), mode
+        ws = torch.empty((max(M.newton_workspace_bytes(n, mode | NEWTON_KEEP_FACTOR), 1),), dtype=torch.uint8,
+                         device="cuda")
+        xk, ik = M.newton_solve(J, h, b1, NEWTON_GAMMA, mode=mode | NEWTON_KEEP_FACTOR, workspace=ws)
+        x1, i1 = M.newton_solve(J, h, b1, NEWTON_GAMMA, mode=mode)
+        for b in (b2, b1, b2):             # several solves with one kept factor
+            xr, ir = M.newton_solve(J, h, b, NEWTON_GAMMA, mode=mode | NEWTON_REUSE_FACTOR, workspace=ws)
+            xf, i_f = M.newton_solve(J, h, b, NEWTON_GAMMA, mode=mode)
+            torch.cuda.synchronize()
+            assert torch.equal(xr, xf), mode
+            assert torch.equal(ir[:n], i_f[:n]), mode
+        assert torch.equal(xk, x1) and torch.equal(ik[:n], i1[:n]), mode
