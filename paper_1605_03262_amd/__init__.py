@@ -135,7 +135,11 @@ class Mechanism:
 
     def newton_solve(self, jac, h, rhs, gamma: float, mode: int = NEWTON_MIXED,
                      max_refine: int = 10, rtol: float = 1e-14, workspace=None):
-        """Solve (I - h gamma J) x = rhs per state; returns (x, info)."""
+        """Solve (I - h gamma J) x = rhs per state; returns (x, info).
+        `mode` is NEWTON_FP64 or NEWTON_MIXED, optionally or-ed with
+        NEWTON_KEEP_FACTOR (keep the factor in `workspace`, sized by
+        newton_workspace_bytes(n, mode)) or NEWTON_REUSE_FACTOR (solve with
+        the factor the previous call left in the same workspace)."""
         torch = _torch()
         N = self.n_species
         ld = rhs.stride(0)
