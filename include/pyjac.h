@@ -162,8 +162,9 @@ pyjac_status pyjac_eval_jacobian_fd(const pyjac_mech* mech, int64_t n_states, in
  * phi_out [N][ld] (may alias phi).  dnorm [3][ld] (or NULL) receives each
  * stage's last Newton increment max_e |dz_e|, a convergence indicator.
  * workspace: device memory of pyjac_sdirk3_workspace_bytes(mech, n, ld, mode).
- * Errors: PYJAC_E_INVALID (NULL arrays, n < 0, ld < n, newton_iters outside
- * [1, 16], bad mode), PYJAC_E_WORKSPACE, and those of the calls it makes. */
+ * n_states == 0 is a no-op (the arrays may then be NULL).  Errors:
+ * PYJAC_E_INVALID (NULL arrays, n < 0, ld < n, newton_iters outside [1, 16],
+ * bad mode), PYJAC_E_WORKSPACE, and those of the calls it makes. */
 size_t pyjac_sdirk3_workspace_bytes(const pyjac_mech* mech, int64_t n_states, int64_t ld, int32_t mode);
 pyjac_status pyjac_sdirk3_step(const pyjac_mech* mech, int64_t n_states, int64_t ld, const double* phi,
                                const double* p, const double* h, int32_t newton_iters, int32_t mode,

@@ -129,11 +129,12 @@ pyjac_status pyjac_sdirk3_step(const pyjac_mech* m, int64_t n, int64_t ld, const
                                const double* h, int32_t newton_iters, int32_t mode, double* phi_out,
                                double* dnorm, void* workspace, size_t workspace_bytes, void* stream) {
   using namespace pyjac;
-  if (!m || !phi || !p || !h || !phi_out) return fail(PYJAC_E_INVALID, "NULL mechanism or array");
+  if (!m) return fail(PYJAC_E_INVALID, "mechanism handle is NULL");
   if (n < 0 || ld < n) return fail(PYJAC_E_INVALID, "need 0 <= n_states <= ld");
   if (newton_iters < 1 || newton_iters > 16) return fail(PYJAC_E_INVALID, "newton_iters must be in [1, 16]");
   if (mode != 0 && mode != 1) return fail(PYJAC_E_INVALID, "mode must be 0 or 1");
-  if (n == 0) return PYJAC_OK;
+  if (n == 0) return PYJAC_OK;         // empty batch: the arrays may be NULL
+  if (!phi || !p || !h || !phi_out) return fail(PYJAC_E_INVALID, "NULL array argument");
   const SdirkLayout L = sdirk_layout(m, n, ld, mode);
   if (!workspace || workspace_bytes < L.total)
     return fail(PYJAC_E_WORKSPACE, "workspace smaller than pyjac_sdirk3_workspace_bytes");

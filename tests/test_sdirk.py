@@ -128,3 +128,39 @@ def test_gpu_step_arguments():
     with pytest.raises(PyjacError, match="WORKSPACE"):
         M.sdirk3_step(d(phi), d(p), d(np.full(4, 1e-8)), workspace=ws)
     assert _lib.pyjac_sdirk3_workspace_bytes(M.handle, 4, 3, 0) == 0      # ld < n
+
+
+@pytest.mark.gpu
+def test_gpu_step_batch_independence(oracle_built):
+    """A state's step depends only on its own inputs: the same bits alone,
+    permuted in the batch, or with ld > n; n = 0 is a no-op."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import RefMech
+    from paper_1605_03262_amd import Mechanism
+    mech = config_mechanism(1)
+    ref = RefMech(text=mech.to_text())
+    n = 33
+    phi, p = config_states(1, n)
+    h = step_sizes(ref, phi, p, np.full(n, 1.0))
+    M = Mechanism(text=mech.to_text())
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()    # noqa: E731
+    base = M.sdirk3_step(d(phi), d(p), d(h))[0].cpu().numpy()
+    perm = np.random.default_rng(1).permutation(n)
+    yp = M.sdirk3_step(d(phi[:, perm]), d(p[perm]), d(h[perm]))[0].cpu().numpy()
+    assert np.array_equal(yp, base[:, perm])
+    for s in (0, 32):
+        ys = M.sdirk3_step(d(phi[:, s:s + 1]), d(p[s:s + 1]), d(h[s:s + 1]))[0].cpu().numpy()
+        assert np.array_equal(ys[:, 0], base[:, s])
+    ld = 40                                  # padded rows: extra columns hold other states
+    phl = np.concatenate([phi, phi[:, :ld - n]], axis=1)
+    pl = np.concatenate([p, p[:ld - n]])
+    hl = np.concatenate([h, h[:ld - n]])
+    dphl = d(phl)
+    out = torch.full_like(dphl, -1.0)
+    M.sdirk3_step(dphl[:, :n], d(pl), d(hl), out=out[:, :n])
+    o = out.cpu().numpy()
+    assert np.array_equal(o[:, :n], base) and np.all(o[:, n:] == -1.0)
+    M.sdirk3_step(dphl[:, :0], d(pl), d(hl))           # n = 0: returns without launching
+    torch.cuda.synchronize()
