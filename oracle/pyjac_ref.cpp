@@ -40,6 +40,9 @@
 //   * Chebyshev polynomials are evaluated by the three-term recurrences for
 //     T_n (first kind) and U_n (second kind), without clamping.
 //   * NASA range: T <= T_mid uses the low-temperature coefficients.
+//   * P_r <= 0 (no collider present): the Troe and SRI blending functions take
+//     their limits as P_r -> 0+ (log10 P_r -> -inf), and the derivatives of c
+//     are written so that nothing divides by P_r (Sec. 2.3.3, Sec. 3.1).
 //   * SI-kmol units: R = 8314.462618 J/(kmol K), p_atm = 101325 Pa.
 //
 // The RHS is a template over the scalar type so the same code runs in
@@ -302,6 +305,11 @@ template <class S> struct State {
   int N;
   S T, W, rho, cp;
   std::vector<S> Y, X, cpR, hRT, sR;   // all N species
+  // real parts of the concentrations, formed from the real parts of rho and
+  // Y, for branch decisions only: in a complex-step evaluation the real part
+  // of rho * Y carries an O(h^2) term that would misplace the sign test of an
+  // exactly zero concentration
+  std::vector<double> Xre;
 };
 
 template <class S> void thermo(const Mech& m, const S& T, S* cpR, S* hRT, S* sR) {
@@ -330,6 +338,8 @@ template <class S> void make_state(const Mech& m, const S& T, double p, const S*
   st.rho = S(p) * st.W / (S(kR) * T);                             // Eq. (state)
   st.X.resize(N);
   for (int k = 0; k < N; ++k) st.X[k] = st.rho * st.Y[k] / S(m.W[k]);   // [X_k]
+  st.Xre.resize(N);
+  for (int k = 0; k < N; ++k) st.Xre[k] = double(re(st.rho)) * double(re(st.Y[k])) / m.W[k];
   st.cpR.resize(N); st.hRT.resize(N); st.sR.resize(N);
   thermo(m, T, st.cpR.data(), st.hRT.data(), st.sR.data());
   st.cp = S(0);
@@ -404,20 +414,36 @@ template <class S> void reaction_values(const Mech& m, int i, const State<S>& st
   if (r.kind == THD) v.c = v.E;
   if (r.kind == FALLOFF || r.kind == CHEMACT) {
     v.Pr = v.k0 / v.kinf * v.E;                                     // Eq. (pr_i)
+    // P_r <= 0 (an absent single-species collider, or one driven slightly
+    // negative by rounding): F takes its limit as P_r -> 0+, where log10 P_r
+    // -> -inf.  Troe: A/B -> 1/(-0.14), so F -> F_cent^(1/(1 + 1/0.14^2));
+    // SRI: X -> 0, so F -> d T^e.
+    double Ere = 0;
+    if (r.collider_species) Ere = st.Xre[r.m];
+    else for (int j = 0; j < m.N; ++j) Ere += r.alpha[j] * st.Xre[j];
+    const bool pos = double(re(v.k0 / v.kinf)) * Ere > 0;
     if (r.blend == LIND) v.F = S(1);
     else if (r.blend == TROE) {
       const auto& t = r.troe;
       v.Fcent = S(1 - t[0]) * exp(-T / S(t[1])) + S(t[0]) * exp(-T / S(t[2]));
       if (t.size() > 3) v.Fcent += exp(-S(t[3]) / T);
-      S lF = log10s(v.Fcent), lP = log10s(v.Pr);
-      v.At = lP - S(0.67) * lF - S(0.4);
-      v.Bt = S(0.806) - S(1.1762) * lF - S(0.14) * lP;
-      v.F = pow(v.Fcent, S(1) / (S(1) + (v.At / v.Bt) * (v.At / v.Bt)));
+      if (pos) {
+        S lF = log10s(v.Fcent), lP = log10s(v.Pr);
+        v.At = lP - S(0.67) * lF - S(0.4);
+        v.Bt = S(0.806) - S(1.1762) * lF - S(0.14) * lP;
+        v.F = pow(v.Fcent, S(1) / (S(1) + (v.At / v.Bt) * (v.At / v.Bt)));
+      } else {
+        v.F = pow(v.Fcent, S(1) / (S(1) + S(1.0 / (0.14 * 0.14))));
+      }
     } else {
       const auto& s = r.sri;
       double d = s.size() > 3 ? s[3] : 1.0, e = s.size() > 4 ? s[4] : 0.0;
-      S lP = log10s(v.Pr);
-      v.Xs = S(1) / (S(1) + lP * lP);
+      if (pos) {
+        S lP = log10s(v.Pr);
+        v.Xs = S(1) / (S(1) + lP * lP);
+      } else {
+        v.Xs = S(0);
+      }
       v.sri_base = S(s[0]) * exp(-S(s[1]) / T) + exp(-T / S(s[2]));
       v.F = S(d) * pow(T, S(e)) * pow(v.sri_base, v.Xs);
     }
@@ -552,10 +578,22 @@ void jacobian(const Mech& m, double T, double p, const double* y, double* J /* N
     for (auto& [k, n] : r.prod) { sr += n; pr *= ipow(st.X[k], n); }
     dRdT[i] = dkfdT * pf - x.kf * pf * sf / T - (dkrdT * pr - x.kr * pr * sr / T);
     // --- dc/dT and dc/dY (Sec. 3.1)
-    double dPrdT = 0, dFdT = 0, dFdPr_over_F = 0;   // dF/dPr / F
+    double dPrdT = 0, dlnPrdT = 0, dFdT = 0, dFdPr_over_F = 0;   // dF/dPr / F
     if (r.kind == FALLOFF || r.kind == CHEMACT) {
-      dPrdT = x.Pr / T * (r.low.b - r.high.b + (r.low.Ta - r.high.Ta) / T - 1);     // Eq. (dPridT)
-      if (r.blend == TROE) {
+      dlnPrdT = (r.low.b - r.high.b + (r.low.Ta - r.high.Ta) / T - 1) / T;       // Eq. (dPridT) / P_r
+      dPrdT = x.Pr * dlnPrdT;
+      if (x.Pr <= 0) {
+        // P_r -> 0+ limit (see reaction_values): F depends on T alone, and
+        // every P_r-derivative of ln F vanishes in the limit
+        if (r.blend == TROE) {
+          const auto& t = r.troe;
+          double dFc_dT = -(1 - t[0]) / t[1] * std::exp(-T / t[1]) - t[0] / t[2] * std::exp(-T / t[2]);
+          if (t.size() > 3) dFc_dT += t[3] / (T * T) * std::exp(-t[3] / T);
+          dFdT = x.F / (x.Fcent * (1 + 1 / (0.14 * 0.14))) * dFc_dT;
+        } else if (r.blend == SRI) {
+          dFdT = x.F * ((r.sri.size() > 4 ? r.sri[4] : 0.0) / T);
+        }
+      } else if (r.blend == TROE) {
         const auto& t = r.troe;
         double ratio2 = (x.At / x.Bt) * (x.At / x.Bt);
         double dA_dFc = -0.67 / (x.Fcent * kLn10), dB_dFc = -1.1762 / (x.Fcent * kLn10);
@@ -581,7 +619,7 @@ void jacobian(const Mech& m, double T, double p, const double* y, double* J /* N
       }
     }
     if (r.kind == THD) dcdT[i] = -x.c / T;
-    else if (r.kind == FALLOFF) dcdT[i] = x.c * (dPrdT / (x.Pr * (1 + x.Pr)) + dFdT / x.F);
+    else if (r.kind == FALLOFF) dcdT[i] = x.c * (dlnPrdT / (1 + x.Pr) + dFdT / x.F);
     else if (r.kind == CHEMACT) dcdT[i] = x.c * (-dPrdT / (1 + x.Pr) + dFdT / x.F);
     else dcdT[i] = 0;
     double* dc = &dcdY[(size_t)i * (N - 1)];
@@ -595,7 +633,8 @@ void jacobian(const Mech& m, double T, double p, const double* y, double* J /* N
         else {
           double dPr = x.k0 / x.kinf * dE;                                  // Eq. (dPridY)
           double dFoverF = dFdPr_over_F * dPr;                               // dF/dY_j / F
-          if (r.kind == FALLOFF) dc[j] = x.c * (dPr / (x.Pr * (1 + x.Pr)) + dFoverF);
+          // d/dY_j of P_r/(1+P_r) F and of F/(1+P_r): (1+P_r)^-2 dP_r F plus c dF/F
+          if (r.kind == FALLOFF) dc[j] = x.F / ((1 + x.Pr) * (1 + x.Pr)) * dPr + x.c * dFoverF;
           else dc[j] = x.c * (-dPr / (1 + x.Pr) + dFoverF);
         }
       }

@@ -1,17 +1,25 @@
-"""Build libpyjac_mi355x.so in-tree with hipcc for gfx950."""
+"""Build libpyjac_mi355x.so in-tree with hipcc for gfx950.
+
+Each source is compiled to its own object in parallel (every translation
+unit carries its own device code, no relocatable device code is needed), then
+the objects are linked into the shared library.
+"""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(os.path.dirname(HERE), "_build", "obj")
 LIB = os.path.join(HERE, "libpyjac_mi355x.so")
-SOURCES = ["loader.cpp", "chemkin.cpp", "kinetics.hip", "newton.hip", "fd.hip", "integ.hip", "serve.cpp", "api.hip"]
+SOURCES = ["loader.cpp", "chemkin.cpp", "kinetics.hip", "sparse.hip", "newton.hip", "fd.hip",
+           "integ.hip", "serve.cpp", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     # packed FP32 (v_pk_*_f32) is disabled for all device code on this target
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -23,15 +31,33 @@ def sources():
     return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + sources()
+def _compile(src: str, verbose: bool):
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
+    return obj, res
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = sources()
+    jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        results = list(pool.map(lambda s: _compile(s, verbose), srcs))
+    failed = [(o, r) for o, r in results if r.returncode != 0]
+    for _, r in failed:
+        sys.stderr.write(r.stdout + r.stderr)
+    if failed:
+        raise RuntimeError("hipcc build of libpyjac_mi355x.so failed")
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + \
+          [o for o, _ in results]
+    res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc build of libpyjac_mi355x.so failed")
+        raise RuntimeError("link of libpyjac_mi355x.so failed")
     os.replace(tmp, LIB)
     return LIB
 
