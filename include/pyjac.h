@@ -98,12 +98,15 @@ pyjac_status pyjac_chemkin_to_text(const char* mech_text, const char* thermo_tex
 pyjac_status pyjac_mech_load_chemkin(const char* mech_path, const char* thermo_path, int32_t hip_device,
                                      pyjac_mech** out);
 
-/* Sizes and a 64-bit content hash of the parsed mechanism (any out may be NULL). */
+/* Sizes and a 64-bit content hash of the parsed mechanism (any out may be
+ * NULL): N species and N_R reactions as in Sec. 2 (the state has N entries,
+ * Eq. vars, and the Jacobian N x N). */
 pyjac_status pyjac_mech_info(const pyjac_mech* mech, int32_t* n_species, int32_t* n_reactions,
                              uint64_t* content_hash);
 
-/* Synchronizes the mechanism's device, then frees its tables and the handle.
- * NULL is accepted and ignored. */
+/* Synchronizes the mechanism's device, then frees its tables (the per-mechanism
+ * data of Sec. 2.2-2.3 held on the device) and the handle.  NULL is accepted
+ * and ignored. */
 pyjac_status pyjac_mech_free(pyjac_mech* mech);
 
 /* Reaction rates, production rates and the RHS (Sec. 2.1 Eqs. ode/dTdt,
@@ -177,7 +180,9 @@ pyjac_status pyjac_sdirk3_step(const pyjac_mech* mech, int64_t n_states, int64_t
  * Returns 0 for a bad handle or mode. */
 size_t pyjac_newton_workspace_bytes(const pyjac_mech* mech, int64_t n_states, int32_t mode);
 
-/* Batched solve of the Newton system of an implicit integrator step,
+/* Batched solve of the Newton system of an implicit integrator step (the
+ * consumer of the Jacobian that Sec. 1 gives as the method's motivation:
+ * implicit integration of stiff chemistry needs J for its Newton iterations),
  * A x = rhs with A = I - h_s * gamma * J_s for every state s (N x N, FP64
  * Jacobian as written by pyjac_eval_jacobian, same layout and ld).
  *   h      [ld]      per-state step size

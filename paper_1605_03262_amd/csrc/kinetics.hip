@@ -225,22 +225,31 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
           dFc += fp[3] * iT * iT * e2;
         }
         const double lnFc = log(Fc);
-        const double lFc = lnFc * kInvLn10, lPr = log(Pr) * kInvLn10;
-        const double At = lPr - 0.67 * lFc - 0.4;
-        const double Bt = 0.806 - 1.1762 * lFc - 0.14 * lPr;
-        const double r = At / Bt, den = 1.0 + r * r;
-        F = exp(lnFc / den);
-        const double den2B3 = den * den * Bt * Bt * Bt;
-        Lam = -lnFc * 2.0 * At * (Bt + 0.14 * At) * kInvLn10 / den2B3;
-        const double dAB = (-0.67 * Bt + 1.1762 * At) * kInvLn10 / Fc;   // (dA/dFc B - A dB/dFc)
-        const double dlnF_dFc = 1.0 / (Fc * den) - lnFc * 2.0 * At * dAB / den2B3;
-        dlnFdT = dlnF_dFc * dFc;
+        if (Pr > 0.0) {
+          const double lFc = lnFc * kInvLn10, lPr = log(Pr) * kInvLn10;
+          const double At = lPr - 0.67 * lFc - 0.4;
+          const double Bt = 0.806 - 1.1762 * lFc - 0.14 * lPr;
+          const double r = At / Bt, den = 1.0 + r * r;
+          F = exp(lnFc / den);
+          const double den2B3 = den * den * Bt * Bt * Bt;
+          Lam = -lnFc * 2.0 * At * (Bt + 0.14 * At) * kInvLn10 / den2B3;
+          const double dAB = (-0.67 * Bt + 1.1762 * At) * kInvLn10 / Fc;   // (dA/dFc B - A dB/dFc)
+          const double dlnF_dFc = 1.0 / (Fc * den) - lnFc * 2.0 * At * dAB / den2B3;
+          dlnFdT = dlnF_dFc * dFc;
+        } else {
+          // no collider present: the limit P_r -> 0+, where A/B -> -1/0.14
+          // and the P_r-derivative term of ln F vanishes
+          constexpr double den0 = 1.0 + 1.0 / (0.14 * 0.14);
+          F = exp(lnFc / den0);
+          dlnFdT = dFc / (Fc * den0);
+        }
       } else if (blend == B_SRI) {
         const double ea = exp(-fp[1] * iT), ec = exp(-T / fp[2]);
         const double base = fp[0] * ea + ec;
         const double dbase = fp[0] * fp[1] * iT * iT * ea - ec / fp[2];
-        const double lPr = log(Pr) * kInvLn10;
-        const double Xs_ = 1.0 / (1.0 + lPr * lPr);
+        // P_r <= 0 (no collider present) takes the limit P_r -> 0+: X -> 0
+        const double lPr = Pr > 0.0 ? log(Pr) * kInvLn10 : 0.0;
+        const double Xs_ = Pr > 0.0 ? 1.0 / (1.0 + lPr * lPr) : 0.0;
         const double lnb = log(base);
         F = fp[3] * exp(fp[4] * lT + Xs_ * lnb);
         Lam = -lnb * Xs_ * Xs_ * 2.0 * lPr * kInvLn10;
@@ -255,7 +264,9 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
       } else {
         c = F / (1.0 + Pr);
         Phi = -Pr / (1.0 + Pr) + Lam;
-        psi = c * Phi / E;
+        // dc/dE = c (-ratio/(1+P_r) + dlnF/dP_r ratio); the second term is
+        // Lam/E, zero in the P_r -> 0+ limit taken when no collider is present
+        psi = -c * ratio / (1.0 + Pr) + (Pr > 0.0 ? c * Lam / E : 0.0);
       }
       dcdT = c * (Phi * dlnPr + dlnFdT);
     }

@@ -240,16 +240,18 @@ void scheduler_loop(pyjac_server* S) {
   hipSetDevice(S->device);
   std::unique_lock<std::mutex> lk(S->mu);
   while (true) {
+    // Wake for a pending request once a stream is free, or to exit once a
+    // stop has been requested and nothing is pending.  Pending requests keep
+    // the loop alive after a stop; it then still waits (releasing the lock)
+    // until the completion thread frees a stream.
     S->cv_sched.wait(lk, [&] {
-      if (S->stop) return true;
-      if (S->pending.empty()) return false;
+      if (S->pending.empty()) return S->stop;
       for (int b : S->stream_busy) if (!b) return true;
       return false;
     });
-    if (S->stop && S->pending.empty()) break;
+    if (S->pending.empty()) break;
     int sidx = -1;
     for (int i = 0; i < S->n_streams; ++i) if (!S->stream_busy[i]) { sidx = i; break; }
-    if (sidx < 0) continue;
     // Form a batch: the head request's mechanism and mode, then later requests
     // with the same mechanism/mode, in arrival order, while the packed batch
     // stays within max_batch states and fits the free arena.

@@ -1,6 +1,7 @@
 import os
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -43,3 +44,33 @@ def split_form_mech(seed, reactive_last=False):
     return tiny_mechanism(seed, kinds, n_species=40, reactive_last=reactive_last,
                           rev_mix={"kc": 2, "explicit": 1, "irrev": 1},
                           elements=("C", "H", "O", "N"), bounds={"C": 2, "H": 5, "O": 3, "N": 1})
+
+
+# Falloff and chemically activated classes with a blending function.
+BLENDED = [f"{a}_{b}" for a in ("falloff", "chemact") for b in ("lindemann", "troe", "sri")]
+
+
+def species_collider_mech(kind, seed):
+    """One reaction of the class with a single-species collider m, plus two
+    elementary reactions; m is not the implied last species."""
+    for attempt in range(40):
+        mech = tiny(seed + 1000 * attempt, {kind: 1, "elementary": 2}, collider_probs=(0.0, 1.0))
+        r = next(x for x in mech.reactions if x.kind == kind)
+        if r.collider_species != mech.n_species - 1:
+            return mech, r.collider_species
+    raise RuntimeError("no mechanism with a non-last collider species")
+
+
+def zero_collider_states(mech, m, seed, values=(0.0, 0.0, -1e-14, 0.0)):
+    phi, p = _draw_states(seed, mech.n_species, len(values), dirichlet=0.7)
+    for s, v in enumerate(values):
+        phi[1 + m, s] = v
+    if len(values) > 3:
+        phi[1:, 3] = np.where(np.arange(mech.n_species - 1) == m, 0.0, phi[1:, 3])
+        phi[1 + (m + 1) % (mech.n_species - 1), 3] = 0.0     # a second zero species
+    return phi, p
+
+
+def _draw_states(*a, **k):
+    from synth import draw_states
+    return draw_states(*a, **k)

@@ -96,7 +96,9 @@ def check_rates(og, orf, mech, phi, p, label=""):
         err = np.abs(g - r) <= RATE_TOL * np.abs(r) + 1e-300
         assert err.all(), f"{label} {k}: worst rel {np.max(np.abs(g - r) / (np.abs(r) + 1e-300)):.3e}"
     nf, nr = mech.stoich()
-    gross = np.abs(nr - nf) @ (np.abs(orf["pres_mod"]) * (orf["rop_f"] + orf["rop_r"]))
+    # gross magnitudes from absolute values: a concentration driven below zero
+    # (a rounding-negative mass fraction) makes R_f or R_r negative
+    gross = np.abs(nr - nf) @ (np.abs(orf["pres_mod"]) * (np.abs(orf["rop_f"]) + np.abs(orf["rop_r"])))
     assert np.all(np.abs(og["wdot"] - orf["wdot"]) <= RATE_TOL * gross + 1e-300), label
     W = mech.molecular_weights()
     T = phi[0]

@@ -20,7 +20,7 @@ import mpmath as mp
 import numpy as np
 import pytest
 
-from conftest import tiny
+from conftest import BLENDED, species_collider_mech, tiny, zero_collider_states
 from synth import ATM, draw_states
 
 R = 8314.462618
@@ -259,28 +259,6 @@ def test_lindemann_is_troe_with_unit_fcent(Ref, kind):
 
 
 # ---------------------------------------------------- absent collider (P_r = 0)
-BLENDED = [f"{a}_{b}" for a in ("falloff", "chemact") for b in ("lindemann", "troe", "sri")]
-
-
-def species_collider_mech(kind, seed):
-    """One reaction of the class with a single-species collider m, plus two
-    elementary reactions; m is not the implied last species."""
-    for attempt in range(40):
-        mech = tiny(seed + 1000 * attempt, {kind: 1, "elementary": 2}, collider_probs=(0.0, 1.0))
-        r = next(x for x in mech.reactions if x.kind == kind)
-        if r.collider_species != mech.n_species - 1:
-            return mech, r.collider_species
-    raise RuntimeError("no mechanism with a non-last collider species")
-
-
-def zero_collider_states(mech, m, seed, values=(0.0, 0.0, -1e-14, 0.0)):
-    phi, p = draw_states(seed, mech.n_species, len(values), dirichlet=0.7)
-    for s, v in enumerate(values):
-        phi[1 + m, s] = v
-    if len(values) > 3:
-        phi[1:, 3] = np.where(np.arange(mech.n_species - 1) == m, 0.0, phi[1:, 3])
-        phi[1 + (m + 1) % (mech.n_species - 1), 3] = 0.0     # a second zero species
-    return phi, p
 
 
 @pytest.mark.parametrize("kind", BLENDED)

@@ -60,3 +60,27 @@ def test_oversized_request_is_rejected():
     with pytest.raises(PyjacError):
         srv.submit(M, phi, p, h, b, NEWTON_GAMMA)
     srv.close()
+
+
+def test_close_without_waiting_finishes_every_request():
+    """More requests than streams, then close() at once: it returns (no
+    scheduler spin holding the lock while the streams are busy) and every
+    request has completed with its outputs written."""
+    import threading
+    from paper_1605_03262_amd import Mechanism, Server
+    M = Mechanism(text=config_mechanism(0).to_text())
+    srv = Server(hbm_budget_bytes=64 << 20, max_batch_states=40, n_streams=1, max_refine=4, rtol=1e-14)
+    rng = np.random.default_rng(17)
+    outs = []
+    for _ in range(16):
+        phi, p, h, b = _request(rng, M.n_species, 37)
+        rid, x, info = srv.submit(M, phi, p, h, b, NEWTON_GAMMA, mode=0)
+        outs.append((phi, p, h, b, x, info))
+    t = threading.Thread(target=srv.close)
+    t.start()
+    t.join(timeout=60)
+    assert not t.is_alive(), "close() did not return"
+    import torch
+    for phi, p, h, b, x, info in outs:
+        xa, ia = _alone(torch, M, phi, p, h, b, 0, 4, 1e-14)
+        assert np.array_equal(info, ia) and np.array_equal(x, xa)
