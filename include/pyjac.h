@@ -222,6 +222,25 @@ pyjac_status pyjac_newton_factor_solve(const pyjac_mech* mech, int64_t n_states,
                                        int32_t max_refine, double rtol, int32_t* info,
                                        void* workspace, size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as pyjac_newton_factor_solve (same kernels, same results bit for bit)
+ * with its workspace taken from a static device array of
+ * PYJAC_NEWTON_STATIC_SCRATCH_BYTES held by each GPU the library runs on until
+ * the process ends.  No allocation of any kind happens in the call.
+ * mode is 0 or 1 only (the factor-keeping flags are refused, since every call
+ * on a GPU shares that GPU's array).  Calls that overlap on one GPU (other
+ * streams or host threads) race on the array: order them.  Errors:
+ * PYJAC_E_WORKSPACE when n_states needs more than the array holds
+ * (pyjac_newton_workspace_bytes(mech, n_states, mode) >
+ * PYJAC_NEWTON_STATIC_SCRATCH_BYTES), otherwise as pyjac_newton_factor_solve. */
+#define PYJAC_NEWTON_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+pyjac_status pyjac_newton_factor_solve_noalloc(const pyjac_mech* mech, int64_t n_states, int64_t ld,
+                                               const double* jac, const double* h, double gamma,
+                                               const double* rhs, double* x, int32_t mode,
+                                               int32_t max_refine, double rtol, int32_t* info,
+                                               void* stream);
+
 /* Tuning: force the launch shape of one kernel family of this handle
  * (which = 0: rates kernel, 1: Jacobian kernel) to tile_states states per
  * workgroup and `threads` threads per workgroup; tile_states = 0 restores the

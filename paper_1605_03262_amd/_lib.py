@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "PYJAC_OK", -1: "PYJAC_E_INVALID", -2: "PYJAC_E_PARSE",
 EXPORTED = ("pyjac_mech_load", "pyjac_mech_load_string", "pyjac_chemkin_to_text",
             "pyjac_mech_load_chemkin", "pyjac_mech_info", "pyjac_mech_free",
             "pyjac_eval_rates", "pyjac_eval_jacobian", "pyjac_newton_workspace_bytes",
-            "pyjac_newton_factor_solve", "pyjac_mech_set_variant", "pyjac_mech_get_variant",
+            "pyjac_newton_factor_solve", "pyjac_newton_factor_solve_noalloc", "pyjac_mech_set_variant", "pyjac_mech_get_variant",
             "pyjac_mech_autotune", "pyjac_fd_workspace_bytes", "pyjac_eval_jacobian_fd",
             "pyjac_sdirk3_workspace_bytes", "pyjac_sdirk3_step",
             "pyjac_status_string", "pyjac_last_error", "pyjac_serve_create", "pyjac_serve_submit",
@@ -71,6 +71,9 @@ def load_library() -> ctypes.CDLL:
     lib.pyjac_newton_factor_solve.argtypes = [vp, i64, i64, vp, vp, ctypes.c_double, vp, vp, i32,
                                               i32, ctypes.c_double, vp, vp, sz, vp]
     lib.pyjac_newton_factor_solve.restype = st
+    lib.pyjac_newton_factor_solve_noalloc.argtypes = [vp, i64, i64, vp, vp, ctypes.c_double, vp, vp, i32,
+                                                      i32, ctypes.c_double, vp, vp]
+    lib.pyjac_newton_factor_solve_noalloc.restype = st
     lib.pyjac_mech_set_variant.argtypes = [vp, i32, i32, i32]
     lib.pyjac_mech_set_variant.restype = st
     lib.pyjac_mech_get_variant.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -177,6 +180,13 @@ def pyjac_newton_factor_solve(mech, n, ld, jac, h, gamma, rhs, x, mode, max_refi
                                                    max_refine, rtol, info, workspace,
                                                    workspace_bytes, stream),
           "pyjac_newton_factor_solve")
+
+
+def pyjac_newton_factor_solve_noalloc(mech, n, ld, jac, h, gamma, rhs, x, mode, max_refine, rtol, info,
+                                      stream) -> None:
+    check(load_library().pyjac_newton_factor_solve_noalloc(mech, n, ld, jac, h, gamma, rhs, x, mode,
+                                                           max_refine, rtol, info, stream),
+          "pyjac_newton_factor_solve_noalloc")
 
 
 def pyjac_mech_set_variant(mech, which, tile_states, threads) -> None:

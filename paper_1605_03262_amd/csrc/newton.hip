@@ -20,6 +20,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <utility>
 
@@ -880,12 +881,69 @@ hipError_t run_direct(int N, int64_t n, int64_t ld, const double* jac, const dou
   return hipGetLastError();
 }
 
+// Scratch for the no-allocation entry point: a file-scope device array, one
+// copy per GPU, alive until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in symbol): the
+// device address of each GPU's copy is looked up once with the device current
+// and kept per device.
+constexpr size_t kStaticScratchBytes = PYJAC_NEWTON_STATIC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (looked up on the first
+// call per device); NULL with the error recorded on failure.
+void* scratch_for_device(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    fail(PYJAC_E_DEVICE, "device ordinal outside the scratch table");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      fail(PYJAC_E_DEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 }  // namespace pyjac
 
 using namespace pyjac;
 
 extern "C" {
+
+pyjac_status pyjac_newton_factor_solve_noalloc(const pyjac_mech* m, int64_t n, int64_t ld, const double* jac,
+                                               const double* h, double gamma, const double* rhs, double* x,
+                                               int32_t mode, int32_t max_refine, double rtol, int32_t* info,
+                                               void* stream) {
+  if (!m) return fail(PYJAC_E_INVALID, "mechanism handle is NULL");
+  if (mode != 0 && mode != 1)
+    return fail(PYJAC_E_INVALID, "mode must be 0 or 1 (the factor-keeping flags are not accepted here)");
+  if (n < 0 || ld < n) return fail(PYJAC_E_INVALID, "bad n_states / ld");
+  if (n == 0) return PYJAC_OK;
+  const size_t need = pyjac_newton_workspace_bytes(m, n, mode);
+  if (need > kStaticScratchBytes)
+    return fail(PYJAC_E_WORKSPACE, "n_states needs " + std::to_string(need) +
+                                       " bytes of scratch; the static scratch holds " +
+                                       std::to_string(kStaticScratchBytes) +
+                                       " (use pyjac_newton_factor_solve with a workspace)");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != mech_device(m))
+    return fail(PYJAC_E_INVALID, "current HIP device differs from the mechanism's device");
+  void* ptr = scratch_for_device(cur);
+  if (!ptr) return PYJAC_E_DEVICE;
+  // the kernels clear the counters they use (no memset), so the contents a
+  // previous call left in the array do not matter
+  return pyjac_newton_factor_solve(m, n, ld, jac, h, gamma, rhs, x, mode, max_refine, rtol, info, ptr,
+                                   kStaticScratchBytes, stream);
+}
 
 size_t pyjac_newton_workspace_bytes(const pyjac_mech* m, int64_t n, int32_t mode) {
   const bool keep = (mode & PYJAC_NEWTON_KEEP_FACTOR) != 0;
