@@ -38,7 +38,8 @@ constexpr double kR = kGasConstant;
 constexpr double kLn10 = 2.302585092994045684;
 constexpr double kInvLn10 = 0.4342944819032518277;
 constexpr int NSC = 16;
-enum { SC_T = 0, SC_IT, SC_LT, SC_P, SC_LP, SC_L10P, SC_RHO, SC_W, SC_M, SC_CP, SC_DCP, SC_SHW, SC_J00, SC_HA, SC_HB };
+enum { SC_T = 0, SC_IT, SC_LT, SC_P, SC_LP, SC_L10P, SC_RHO, SC_W, SC_M, SC_CP, SC_DCP, SC_SHW, SC_J00, SC_HA, SC_HB,
+       SC_IRHO };
 
 // LDS layout in doubles; each entry counts rows of TS doubles.
 struct TileLayout {
@@ -59,11 +60,11 @@ struct TileLayout {
     chunk = redA;                           // phase B reuses the phase-A reduction rows
     int endB = chunk + (jac ? 4 : 1) * Gr;
     int endA = redA + (jac ? 2 : 1) * N;
-    WA = alias;                             // WA and WB interleaved: [k][s][2]
+    WA = alias;                             // WA and WB interleaved: [k][s][2], k = 0..N (row N: slack)
     WB = WA;
-    JT = WA + (jac ? 2 * N : 0);
-    H = JT + (jac ? N : 0);
-    redC = H + (jac ? N : 0);
+    JT = WA + (jac ? 2 * (N + 1) : 0);
+    H = JT + (jac ? N : 0);                 // k = 0..N (row N: slack)
+    redC = H + (jac ? N + 1 : 0);
     int endC = redC + (jac ? 2 : 1) * N;
     int e = endB > endA ? endB : endA;
     rows = e > endC ? e : endC;
@@ -73,12 +74,6 @@ struct TileLayout {
 struct RxnResult {
   double q, thT, a, b, KF, KR, G, Rf, Rr, c;
 };
-
-__device__ inline double ipow_small(double x, int n) {
-  double r = 1.0;
-  for (int c = 0; c < n; ++c) r *= x;
-  return r;
-}
 
 // NASA-7 coefficient pointer for species k at temperature T.
 __device__ inline const double* nasa_coeffs(const MechDev& md, int k, double T) {
@@ -91,8 +86,8 @@ template <int TS, bool JAC>
 __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const RxnRec* __restrict__ Rg,
                                      const double* Xs,
                                      const double* Bks, const double* dBks, double T, double iT,
-                                     double lT, double lp, double l10p, double rho, double W,
-                                     double M, RxnResult& o) {
+                                     double lT, double lp, double l10p, double rho, double irho,
+                                     double W, double M, RxnResult& o) {
   const int info = R.info;
   const int kind = info & 0xF, blend = (info >> 4) & 0xF, rev = (info >> 8) & 0xF,
             coll = (info >> 12) & 0xF;
@@ -173,16 +168,10 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
     kr = arg[6] * exp(arg[7] * lT - arg[8] * iT);
     Dr = arg[7] + arg[8] * iT;
   }
-  // ---- mass-action products
-  const int* sd = R.side;
-  double pf = 1.0, pr = 1.0;
-#pragma unroll
-  for (int q = 0; q < kMaxSide; ++q) {
-    int v = sd[q];
-    if (v != -1) pf *= ipow_small(Xs[(v & 0xFFFF) * TS], v >> 16);
-    int w = sd[kMaxSide + q];
-    if (w != -1) pr *= ipow_small(Xs[(w & 0xFFFF) * TS], w >> 16);
-  }
+  // ---- mass-action products over the molecule lists (absent molecules read X[N] = 1)
+  const int* mo = R.mol;
+  const double pf = Xs[mo[0] * TS] * Xs[mo[1] * TS] * Xs[mo[2] * TS];
+  const double pr = Xs[mo[3] * TS] * Xs[mo[4] * TS] * Xs[mo[5] * TS];
   const double Rf = kf * pf, Rr = kr * pr, Rn = Rf - Rr;
   // ---- pressure modification (Sec. 2.3.2, 2.3.3) and its derivatives
   double c = 1.0, psi = 0.0, dcdT = 0.0, E = 0.0;
@@ -215,10 +204,10 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
       double F = 1.0, Lam = 0.0, dlnFdT = 0.0;
       const double* fp = Rg->fpar;
       if (blend == B_TROE) {
-        const double a = fp[0];
-        const double e3 = exp(-T / fp[1]), e1 = exp(-T / fp[2]);
+        const double a = fp[0], r3 = Rg->frcp[0], r1 = Rg->frcp[1];
+        const double e3 = exp(-T * r3), e1 = exp(-T * r1);
         double Fc = (1.0 - a) * e3 + a * e1;
-        double dFc = -(1.0 - a) / fp[1] * e3 - a / fp[2] * e1;
+        double dFc = -(1.0 - a) * r3 * e3 - a * r1 * e1;
         if (info & F_TROE_T2) {
           double e2 = exp(-fp[3] * iT);
           Fc += e2;
@@ -229,12 +218,13 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
           const double lFc = lnFc * kInvLn10, lPr = log(Pr) * kInvLn10;
           const double At = lPr - 0.67 * lFc - 0.4;
           const double Bt = 0.806 - 1.1762 * lFc - 0.14 * lPr;
-          const double r = At / Bt, den = 1.0 + r * r;
-          F = exp(lnFc / den);
-          const double den2B3 = den * den * Bt * Bt * Bt;
-          Lam = -lnFc * 2.0 * At * (Bt + 0.14 * At) * kInvLn10 / den2B3;
-          const double dAB = (-0.67 * Bt + 1.1762 * At) * kInvLn10 / Fc;   // (dA/dFc B - A dB/dFc)
-          const double dlnF_dFc = 1.0 / (Fc * den) - lnFc * 2.0 * At * dAB / den2B3;
+          const double iBt = 1.0 / Bt, iFc = 1.0 / Fc;
+          const double r = At * iBt, den = 1.0 + r * r, iden = 1.0 / den;
+          F = exp(lnFc * iden);
+          const double iden2B3 = iden * iden * iBt * iBt * iBt;          // 1 / (den^2 B^3)
+          Lam = -lnFc * 2.0 * At * (Bt + 0.14 * At) * kInvLn10 * iden2B3;
+          const double dAB = (-0.67 * Bt + 1.1762 * At) * kInvLn10 * iFc;   // (dA/dFc B - A dB/dFc)
+          const double dlnF_dFc = iFc * iden - lnFc * 2.0 * At * dAB * iden2B3;
           dlnFdT = dlnF_dFc * dFc;
         } else {
           // no collider present: the limit P_r -> 0+, where A/B -> -1/0.14
@@ -244,9 +234,10 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
           dlnFdT = dFc / (Fc * den0);
         }
       } else if (blend == B_SRI) {
-        const double ea = exp(-fp[1] * iT), ec = exp(-T / fp[2]);
+        const double rc = Rg->frcp[0];
+        const double ea = exp(-fp[1] * iT), ec = exp(-T * rc);
         const double base = fp[0] * ea + ec;
-        const double dbase = fp[0] * fp[1] * iT * iT * ea - ec / fp[2];
+        const double dbase = fp[0] * fp[1] * iT * iT * ea - ec * rc;
         // P_r <= 0 (no collider present) takes the limit P_r -> 0+: X -> 0
         const double lPr = Pr > 0.0 ? log(Pr) * kInvLn10 : 0.0;
         const double Xs_ = Pr > 0.0 ? 1.0 / (1.0 + lPr * lPr) : 0.0;
@@ -257,16 +248,17 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
       }
       const double dlnPr = (arg[4] + arg[5] * iT - 1.0) * iT;   // (1/Pr) dPr/dT
       double Phi;
+      const double i1p = 1.0 / (1.0 + Pr);
       if (kind == K_FALLOFF) {
-        c = Pr / (1.0 + Pr) * F;
-        Phi = 1.0 / (1.0 + Pr) + Lam;
-        psi = ratio * F * Phi / (1.0 + Pr);
+        c = Pr * i1p * F;
+        Phi = i1p + Lam;
+        psi = ratio * F * Phi * i1p;
       } else {
-        c = F / (1.0 + Pr);
-        Phi = -Pr / (1.0 + Pr) + Lam;
+        c = F * i1p;
+        Phi = -Pr * i1p + Lam;
         // dc/dE = c (-ratio/(1+P_r) + dlnF/dP_r ratio); the second term is
         // Lam/E, zero in the P_r -> 0+ limit taken when no collider is present
-        psi = -c * ratio / (1.0 + Pr) + (Pr > 0.0 ? c * Lam / E : 0.0);
+        psi = -c * ratio * i1p + (Pr > 0.0 ? c * Lam / E : 0.0);
       }
       dcdT = c * (Phi * dlnPr + dlnFdT);
     }
@@ -278,7 +270,7 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
   if (JAC) {
     const int sf = R.sum_f, sr = R.sum_r;
     const double dRdT = (Rf * (Df - sf) - Rr * (Dr - sr)) * iT;
-    o.thT = (dcdT * Rn + c * (dRdT + Rn * iT)) / rho;
+    o.thT = (dcdT * Rn + c * (dRdT + Rn * iT)) * irho;
     const double Gv = psi * Rn;
     double kappa = 0.0, beta = 0.0;
     if (coll == C_EFF) {
@@ -291,24 +283,16 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
     o.a = -W * c * (Rf * sf - Rr * sr) + Gv * kappa;
     double b = Gv * beta;
     if (info & F_LAST_SPECIES) {
-      // c (k_f S'_N - k_r S''_N) with S'_N = d(prod [X]^nu')/d[X_N]
+      // c (k_f S'_N - k_r S''_N) with S'_N = d(prod [X]^nu')/d[X_N]: by the
+      // product rule over the molecule list, the sum over the molecules equal
+      // to N of the product of the other two
       const int L = md.N - 1;
       double SfN = 0.0, SrN = 0.0;
-      for (int side = 0; side < 2; ++side) {
-        double S = 0.0;
-        for (int q = 0; q < kMaxSide; ++q) {
-          int v = sd[side * kMaxSide + q];
-          if (v == -1 || (v & 0xFFFF) != L) continue;
-          int nuL = v >> 16;
-          double prod = nuL * ipow_small(Xs[L * TS], nuL - 1);
-          for (int u = 0; u < kMaxSide; ++u) {
-            int w = sd[side * kMaxSide + u];
-            if (w == -1 || u == q) continue;
-            prod *= ipow_small(Xs[(w & 0xFFFF) * TS], w >> 16);
-          }
-          S = prod;
-        }
-        if (side == 0) SfN = S; else SrN = S;
+#pragma unroll
+      for (int q = 0; q < kMaxSide; ++q) {
+        const int u = (q + 1) % kMaxSide, v = (q + 2) % kMaxSide;
+        if (mo[q] == L) SfN += Xs[mo[u] * TS] * Xs[mo[v] * TS];
+        if (mo[kMaxSide + q] == L) SrN += Xs[mo[kMaxSide + u] * TS] * Xs[mo[kMaxSide + v] * TS];
       }
       b += -c * rho * md.invW[L] * (kf * SfN - kr * SrN);
     }
@@ -383,14 +367,17 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
     SC[SC_L10P * TS] = lp * kInvLn10;
     SC[SC_W * TS] = W;
     SC[SC_RHO * TS] = p * W / (kR * T);
+    SC[SC_IRHO * TS] = kR * T / (p * W);
     SC[SC_M * TS] = p / (kR * T);
   }
   __syncthreads();
-  const double T = SC[SC_T * TS], iT = SC[SC_IT * TS], lT = SC[SC_LT * TS];
-  const double rho = SC[SC_RHO * TS], W = SC[SC_W * TS];
 
   // ---- phase A2: concentrations and NASA-7 thermo (Sec. 2.2), B_k of Sec. 2.3.1
+  // (the per-state scalars are read from LDS where they are used, here and in
+  // every reaction chunk, rather than held in registers across phase B)
   for (int k = g; k < N; k += Gr) {
+    const double T = SC[SC_T * TS], iT = SC[SC_IT * TS], lT = SC[SC_LT * TS];
+    const double rho = SC[SC_RHO * TS];
     const double y = X[k * TS];
     X[k * TS] = rho * y * md.invW[k];
     const double* a = nasa_coeffs(md, k, T);
@@ -407,18 +394,25 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
   }
   __syncthreads();
   if (g == 0) {
-    double c0 = 0.0, c1 = 0.0;
-    for (int k = 0; k < N; ++k) {
-      c0 += red[k * TS];
-      if (JAC) c1 += red[(N + k) * TS];
+    // four interleaved partial sums in a fixed order (independent of the
+    // launch shape), so the dependent-add chain is a quarter as long
+    double c0[4] = {0.0, 0.0, 0.0, 0.0}, c1[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k + 4 <= N; k += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        c0[u] += red[(k + u) * TS];
+        if (JAC) c1[u] += red[(N + k + u) * TS];
+      }
     }
-    SC[SC_CP * TS] = c0;
-    SC[SC_DCP * TS] = c1;
+    for (int u = 0; k < N; ++k, ++u) {
+      c0[u] += red[k * TS];
+      if (JAC) c1[u] += red[(N + k) * TS];
+    }
+    SC[SC_CP * TS] = (c0[0] + c0[1]) + (c0[2] + c0[3]);
+    SC[SC_DCP * TS] = (c1[0] + c1[1]) + (c1[2] + c1[3]);
   }
   __syncthreads();
-  const double p = SC[SC_P * TS], lp = SC[SC_LP * TS], l10p = SC[SC_L10P * TS];
-  const double M = SC[SC_M * TS];
-  const double cp = SC[SC_CP * TS];
 
   // ---- phase B: reactions in chunks of Gr, gathered per species (no atomics)
   double* chunk = lds + (size_t)L.chunk * TS + s;
@@ -449,7 +443,9 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
         for (int u = 0; u < 8; ++u) dst[u] = src[u];
       }
       RxnResult o;
-      eval_reaction<TS, JAC>(md, Rr, md.rx + i, X, Bk, dBk, T, iT, lT, lp, l10p, rho, W, M, o);
+      eval_reaction<TS, JAC>(md, Rr, md.rx + i, X, Bk, dBk, SC[SC_T * TS], SC[SC_IT * TS], SC[SC_LT * TS],
+                             SC[SC_LP * TS], SC[SC_L10P * TS], SC[SC_RHO * TS], SC[SC_IRHO * TS],
+                             SC[SC_W * TS], SC[SC_M * TS], o);
       chunk[g * TS] = o.q;
       if (JAC) {
         chunk[(Gr + g) * TS] = o.thT;
@@ -501,7 +497,10 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
   double* JT = lds + (size_t)L.JT * TS + s;
   double* H = lds + (size_t)L.H * TS + s;
   double* redc = lds + (size_t)L.redC * TS + s;
-  const double dcpdT = SC[SC_DCP * TS];
+  const double T = SC[SC_T * TS], iT = SC[SC_IT * TS];
+  const double rho = SC[SC_RHO * TS], irho = SC[SC_IRHO * TS], W = SC[SC_W * TS];
+  const double cp = SC[SC_CP * TS], dcpdT = SC[SC_DCP * TS];
+  const double icp = 1.0 / cp;
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
     const int k = g + q * Gr;
@@ -516,13 +515,13 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
       if (JAC) {
         const double cpk = (a[0] + T * (a[1] + T * (a[2] + T * (a[3] + a[4] * T)))) * kR * md.invW[k];
         const double JTk = Wk * acc[q][1];
-        WAB[k * TS] = make_double2(Wk * (wd * W + acc[q][2]) / rho, Wk * acc[q][3] / rho);
+        WAB[k * TS] = make_double2(Wk * (wd * W + acc[q][2]) * irho, Wk * acc[q][3] * irho);
         JT[k * TS] = JTk;
         H[k * TS] = hk;
-        redc[(N + k) * TS] = (cpk - hk / cp * dcpdT) * Wk * wd / rho + hk * JTk;
+        redc[(N + k) * TS] = (cpk - hk * icp * dcpdT) * Wk * wd * irho + hk * JTk;
       } else if (live) {
         if (wdot_out) wdot_out[(int64_t)k * ld + sg] = wd;
-        if (dphi_out && k < N - 1) dphi_out[(int64_t)(k + 1) * ld + sg] = Wk * wd / rho;
+        if (dphi_out && k < N - 1) dphi_out[(int64_t)(k + 1) * ld + sg] = Wk * wd * irho;
       }
     }
   }
@@ -532,11 +531,20 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
   // two dense coefficients, which give the dense part's share of every
   // temperature-row entry in closed form
   if (g == 0) {
-    double a0 = 0.0, a1 = 0.0;
-    for (int k = 0; k < N; ++k) {
-      a0 += redc[k * TS];
-      if (JAC) a1 += redc[(N + k) * TS];
+    double p0[4] = {0.0, 0.0, 0.0, 0.0}, p1[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k + 4 <= N; k += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        p0[u] += redc[(k + u) * TS];
+        if (JAC) p1[u] += redc[(N + k + u) * TS];
+      }
     }
+    for (int u = 0; k < N; ++k, ++u) {
+      p0[u] += redc[k * TS];
+      if (JAC) p1[u] += redc[(N + k) * TS];
+    }
+    const double a0 = (p0[0] + p0[1]) + (p0[2] + p0[3]), a1 = (p1[0] + p1[1]) + (p1[2] + p1[3]);
     SC[SC_SHW * TS] = a0;
     if (!JAC && live && dphi_out) dphi_out[sg] = -a0 / (rho * cp);
     if (JAC && live) jac[sg] = -a1 / cp;
@@ -565,16 +573,22 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
       // kColBatch records at a time with independent loads; every record is
       // evaluated without branching (markers and padding have coef = 0) and a
       // marker finishes the current row and starts the next.
+      // A lane past the end of the batch computes the last state's values
+      // (it read that state's inputs) and stores them to that state's
+      // elements, the same values the live lane stores, so no store needs a
+      // condition.
       const ColRec* rec = md.colrec + md.col_start[j];
       const int cnt = md.col_start[j + 1] - md.col_start[j];
-      double* outp = jac + (int64_t)(N + j + 1) * ld + sg;       // element (1, j+1)
+      double* outp = jac + (int64_t)(N + j + 1) * ld + sl;       // element (1, j+1)
       const int64_t rstride = (int64_t)N * ld;
       TR = 0.0;
-      double2 ab = WAB[0];
-      double val = ab.x * vj + ab.y;
-      double hk = H[0];
-      double2 abn = WAB[(N > 1 ? 1 : 0) * TS];
-      int k = 0;
+      // row k's (A_k, B_k) and h_k; the arrays hold a slack row N, so the
+      // look-ahead of row k + 1 needs no clamp (its value is then never used)
+      const double2* wab = WAB;
+      const double* hp = H;
+      double val = wab[0].x * vj + wab[0].y;
+      double hk = hp[0];
+      double2 abn = wab[TS];
       ColRec r[kColBatch];
 #pragma unroll
       for (int u = 0; u < kColBatch; ++u) r[u] = rec[u];
@@ -594,20 +608,21 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
 #pragma unroll
         for (int u = 0; u < kColBatch; ++u) {
           val += t[u];
-          if (r[u].x & kColMark) {
-            if (k < N - 1 && live) *outp = val;
+          if (r[u].x & kColMark) {     // ends row k < N - 1 and opens row k + 1
+            *outp = val;
             TR += hk * val;
             outp += rstride;
-            ++k;
             val = abn.x * vj + abn.y;
-            const int kn = k + 1 < N ? k + 1 : N - 1;
-            hk = H[min(k, N - 1) * TS];
-            abn = WAB[kn * TS];
+            wab += TS;
+            hp += TS;
+            hk = *hp;
+            abn = wab[TS];
           }
         }
 #pragma unroll
         for (int u = 0; u < kColBatch; ++u) r[u] = nx[u];
       }
+      TR += hk * val;                  // the placeholder row N - 1 (not stored)
     } else {
       double* colp = jac + (int64_t)(N + j + 1) * ld + sg;       // element (1, j+1): row k = 0
       const int64_t rstride = (int64_t)N * ld;
@@ -694,7 +709,7 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
     }
     const double* aj = nasa_coeffs(md, j, T);
     const double cpj = (aj[0] + T * (aj[1] + T * (aj[2] + T * (aj[3] + aj[4] * T)))) * kR * md.invW[j];
-    if (live) jac[(int64_t)(j + 1) * ld + sg] = -(-(cpj - cpN) / (rho * cp) * Shw + TR) / cp;
+    if (live) jac[(int64_t)(j + 1) * ld + sg] = -(-(cpj - cpN) * irho * icp * Shw + TR) * icp;
   }
 }
 

@@ -320,12 +320,11 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
       rec.info = info;
       rec.orig = r.file_index;
       int sf = 0, sr = 0;
-      for (int q = 0; q < kMaxSide; ++q) {
-        rec.side[q] = q < (int)r.reac.size() ? pack_side(r.reac[q].first, r.reac[q].second) : -1;
-        if (q < (int)r.reac.size()) sf += r.reac[q].second;
-        rec.side[kMaxSide + q] = q < (int)r.prod.size() ? pack_side(r.prod[q].first, r.prod[q].second) : -1;
-        if (q < (int)r.prod.size()) sr += r.prod[q].second;
-      }
+      for (int q = 0; q < 2 * kMaxSide; ++q) rec.mol[q] = N;      // X[N] = 1: an absent molecule
+      for (auto& q : r.reac)
+        for (int c = 0; c < q.second; ++c) rec.mol[sf++] = q.first;
+      for (auto& q : r.prod)
+        for (int c = 0; c < q.second; ++c) rec.mol[kMaxSide + sr++] = q.first;
       rec.sum_f = sf;
       rec.sum_r = sr;
       std::map<int, int> netnu;
@@ -347,11 +346,16 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
         rec.arr[3] = r.low.A / r.high.A; rec.arr[4] = r.low.b - r.high.b; rec.arr[5] = r.low.Ta - r.high.Ta;
       }
       if (r.rev == R_EXPLICIT) { rec.arr[6] = r.revr.A; rec.arr[7] = r.revr.b; rec.arr[8] = r.revr.Ta; }
-      if (r.blend == B_TROE) for (size_t q = 0; q < r.troe.size(); ++q) rec.fpar[q] = r.troe[q];
+      if (r.blend == B_TROE) {
+        for (size_t q = 0; q < r.troe.size(); ++q) rec.fpar[q] = r.troe[q];
+        rec.frcp[0] = 1.0 / r.troe[1];
+        rec.frcp[1] = 1.0 / r.troe[2];
+      }
       if (r.blend == B_SRI) {
         rec.fpar[0] = r.sri[0]; rec.fpar[1] = r.sri[1]; rec.fpar[2] = r.sri[2];
         rec.fpar[3] = r.sri.size() > 3 ? r.sri[3] : 1.0;
         rec.fpar[4] = r.sri.size() > 4 ? r.sri[4] : 0.0;
+        rec.frcp[0] = 1.0 / r.sri[2];
       }
       // collider
       rec.coll_m = (r.coll == C_SPECIES) ? r.m : -1;
@@ -478,8 +482,10 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
         for (int k = 0; k < N; ++k) {
           for (; t < terms.size() && terms[t].j == j && terms[t].k == k; ++t)
             P.colrec.push_back(ColRec{terms[t].coef, N + 1 + terms[t].src, terms[t].x});
-          // end of row k; markers and padding address X[N] = 1 and contribute 0
-          P.colrec.push_back(ColRec{0.0, N, N | (N << 15) | kColMark});
+          // end of row k (the placeholder row N - 1 has no marker: the kernel
+          // finishes it after the stream); markers and padding address X[N] = 1
+          // and contribute 0
+          if (k < N - 1) P.colrec.push_back(ColRec{0.0, N, N | (N << 15) | kColMark});
         }
         while (P.colrec.size() % kColBatch) P.colrec.push_back(ColRec{0.0, N, N | (N << 15)});
       }

@@ -39,14 +39,16 @@ inline int rinfo_kind(int v) { return v & 0xF; }
 // it with independent wide loads before any branch (sorted reaction order).
 struct alignas(16) RxnRec {
   int info, sum_f, sum_r, gslot;          // class/flags, sum nu', sum nu'', G slot or -1
-  int side[2 * kMaxSide];                 // reactants then products: sp | nu << 16, -1 = none
+  int mol[2 * kMaxSide];                  // reactant then product molecules (species index,
+                                          // repeated per unit of nu); N = none (X[N] = 1)
   int net[kMaxNet];                       // sp | nu << 16 (nu signed), -1 = none
   int coll_m, aux0, aux1, orig;           // collider species; efficiency or PLOG range or
                                           // Chebyshev offset; file index of the reaction
   double dnu_lnpr, alphaN_m1;             // sum(nu) ln(p_atm/R); alpha_N - 1
   double arr[kArrStride];
   double fpar[kFparStride];
-  double pad[6];
+  double frcp[2];                         // Troe 1/T***, 1/T*; SRI 1/c (fpar[2])
+  double pad[4];
 };
 static_assert(sizeof(RxnRec) == 256, "RxnRec must stay 256 bytes");
 
@@ -56,8 +58,9 @@ static_assert(sizeof(RxnRec) == 256, "RxnRec must stay 256 bytes");
 // follow directly, so src = N + 1 + (index into P).  A marker has bit kColMark
 // set in x and coef = 0; padding has coef = 0 and src = N.  Two forms:
 //  * every row (col_split = 0): for rows k = 0..N-1 in order, the terms of
-//    (k, j) and a marker (src = N) that ends row k; padding to a multiple of
-//    kColBatch.
+//    (k, j) and, for k < N - 1, a marker (src = N) that ends row k (the
+//    placeholder row N - 1 is finished after the stream); padding to a
+//    multiple of kColBatch.
 //  * present rows only (col_split = 1): bit k of the column's col_flags words
 //    marks row k as present (streamed); the other rows hold the dense part
 //    alone.  The stream is a marker, then for each present row in ascending
