@@ -21,6 +21,7 @@
 //   Jacobian elements, all partial derivatives               Sec. 3.1
 //   evaluation order: species rows (with the last-species
 //   placeholder row) first, then the temperature row         Sec. 3.2, Eqs. (jac_dydt),(jac_dydy),(jac_dt)
+//   constant-volume, concentration-based RHS and Jacobian   Sec. 3.3 (the sparse formulation), Sec. 6
 //
 // The Jacobian is assembled element by element in the naive order of
 // Algorithm 1 (species rows, reactions innermost), NOT in the restructured
@@ -353,19 +354,21 @@ template <class S> struct RxnVals {
   S k0, kinf, E, Pr, F, Fcent, At, Bt, Xs, sri_base;
 };
 
-template <class S> S plog_kf(const Rxn& r, const S& T, double p, int* lo_out, double* frac_out) {
+// The pressure is of the scalar type: in the constant-volume form it is a
+// function of the state (p = R T sum [X_k]).  Bracket decisions use its real part.
+template <class S> S plog_kf(const Rxn& r, const S& T, const S& p, int* lo_out, double* frac_out) {
   using std::log; using std::exp;
   const auto& pts = r.plog;
   int n = (int)pts.size();
   auto lnk = [&](int q) { return log(S(pts[q][1])) + S(pts[q][2]) * log(T) - S(pts[q][3]) / T; };
-  if (n == 1 || p <= pts[0][0]) { *lo_out = 0; *frac_out = -1; return exp(lnk(0)); }
-  if (p >= pts[n - 1][0]) { *lo_out = n - 1; *frac_out = -1; return exp(lnk(n - 1)); }
+  if (n == 1 || re(p) <= pts[0][0]) { *lo_out = 0; *frac_out = -1; return exp(lnk(0)); }
+  if (re(p) >= pts[n - 1][0]) { *lo_out = n - 1; *frac_out = -1; return exp(lnk(n - 1)); }
   int lo = 0;
-  for (int q = 0; q < n - 1; ++q) if (pts[q][0] <= p) lo = q;
-  double frac = (std::log(p) - std::log(pts[lo][0])) / (std::log(pts[lo + 1][0]) - std::log(pts[lo][0]));
-  *lo_out = lo; *frac_out = frac;
+  for (int q = 0; q < n - 1; ++q) if (pts[q][0] <= re(p)) lo = q;
+  S frac = (log(p) - S(std::log(pts[lo][0]))) / S(std::log(pts[lo + 1][0]) - std::log(pts[lo][0]));
+  *lo_out = lo; *frac_out = double(re(frac));
   S l1 = lnk(lo), l2 = lnk(lo + 1);
-  return exp(l1 + (l2 - l1) * S(frac));                        // Eq. (plog)
+  return exp(l1 + (l2 - l1) * frac);                           // Eq. (plog)
 }
 
 template <class S> void cheb_polys(int n, const S& x, S* Tn, S* Un) {
@@ -378,21 +381,21 @@ template <class S> void cheb_polys(int n, const S& x, S* Tn, S* Un) {
   }
 }
 
-template <class S> S cheb_kf(const Rxn& r, const S& T, double p) {
+template <class S> S cheb_kf(const Rxn& r, const S& T, const S& p) {
   using std::pow;
   S Tr = (S(2) / T - S(1.0 / r.Tmin) - S(1.0 / r.Tmax)) / S(1.0 / r.Tmax - 1.0 / r.Tmin);
-  double pr = (2 * std::log10(p) - std::log10(r.Pmin) - std::log10(r.Pmax)) /
-              (std::log10(r.Pmax) - std::log10(r.Pmin));
+  S pr = (S(2) * log10s(p) - S(std::log10(r.Pmin) + std::log10(r.Pmax))) /
+         S(std::log10(r.Pmax) - std::log10(r.Pmin));
   std::vector<S> tT(r.nT), uT(r.nT), tP(r.nP), uP(r.nP);
   cheb_polys(r.nT, Tr, tT.data(), uT.data());
-  cheb_polys(r.nP, S(pr), tP.data(), uP.data());
+  cheb_polys(r.nP, pr, tP.data(), uP.data());
   S lg = S(0);
   for (int i = 0; i < r.nT; ++i)
     for (int j = 0; j < r.nP; ++j) lg += S(r.eta[i * r.nP + j]) * tT[i] * tP[j];   // Eq. (cheb)
   return pow(S(10), lg);
 }
 
-template <class S> void reaction_values(const Mech& m, int i, const State<S>& st, double p, RxnVals<S>& v) {
+template <class S> void reaction_values(const Mech& m, int i, const State<S>& st, const S& p, RxnVals<S>& v) {
   using std::exp; using std::log; using std::pow;
   const Rxn& r = m.rxn[i];
   const S& T = st.T;
@@ -477,8 +480,9 @@ template <class S> void rhs(const Mech& m, const S& T, double p, const S* y, S* 
   for (int k = 0; k < N; ++k) wdot[k] = S(0);
   RxnVals<S> v;
   std::vector<S> q(m.NR);
+  const S pS(p);
   for (int i = 0; i < m.NR; ++i) {
-    reaction_values(m, i, st, p, v);
+    reaction_values(m, i, st, pS, v);
     q[i] = v.c * (v.Rf - v.Rr);
     if (rop_f) rop_f[i] = v.Rf;
     if (rop_r) rop_r[i] = v.Rr;
@@ -493,6 +497,51 @@ template <class S> void rhs(const Mech& m, const S& T, double p, const S* y, S* 
   for (int k = 0; k < N; ++k) hsum += st.hRT[k] * S(kR) * T * wdot[k];    // h_k W_k wdot_k
   dphi[0] = -hsum / (st.rho * st.cp);
   for (int k = 0; k < N - 1; ++k) dphi[k + 1] = S(m.W[k]) * wdot[k] / st.rho;
+}
+
+// dF/dT and (dF/dP_r)/F of the blending function of a falloff or chemically
+// activated reaction (Sec. 2.3.3 definitions, differentiated as in Sec. 3.1),
+// given dP_r/dT along the path of the formulation (it differs between the
+// constant-pressure and the constant-volume forms).
+void blend_derivs(const Rxn& r, const RxnVals<double>& x, double T, double dPrdT, double& dFdT,
+                  double& dFdPr_over_F) {
+  dFdT = 0;
+  dFdPr_over_F = 0;
+  if (x.Pr <= 0) {
+    // P_r -> 0+ limit (see reaction_values): F depends on T alone, and
+    // every P_r-derivative of ln F vanishes in the limit
+    if (r.blend == TROE) {
+      const auto& t = r.troe;
+      double dFc_dT = -(1 - t[0]) / t[1] * std::exp(-T / t[1]) - t[0] / t[2] * std::exp(-T / t[2]);
+      if (t.size() > 3) dFc_dT += t[3] / (T * T) * std::exp(-t[3] / T);
+      dFdT = x.F / (x.Fcent * (1 + 1 / (0.14 * 0.14))) * dFc_dT;
+    } else if (r.blend == SRI) {
+      dFdT = x.F * ((r.sri.size() > 4 ? r.sri[4] : 0.0) / T);
+    }
+  } else if (r.blend == TROE) {
+    const auto& t = r.troe;
+    double ratio2 = (x.At / x.Bt) * (x.At / x.Bt);
+    double dA_dFc = -0.67 / (x.Fcent * kLn10), dB_dFc = -1.1762 / (x.Fcent * kLn10);
+    double dA_dPr = 1.0 / (x.Pr * kLn10), dB_dPr = -0.14 / (x.Pr * kLn10);
+    double lnFc = std::log(x.Fcent);
+    double dF_dFc = x.F * (1.0 / (x.Fcent * (1 + ratio2)) -
+                           lnFc * 2 * x.At / (x.Bt * x.Bt * x.Bt) * (dA_dFc * x.Bt - x.At * dB_dFc) /
+                               ((1 + ratio2) * (1 + ratio2)));
+    double dFc_dT = -(1 - t[0]) / t[1] * std::exp(-T / t[1]) - t[0] / t[2] * std::exp(-T / t[2]);
+    if (t.size() > 3) dFc_dT += t[3] / (T * T) * std::exp(-t[3] / T);
+    double dF_dPr = -x.F * lnFc * 2 * x.At / (x.Bt * x.Bt * x.Bt) * (dA_dPr * x.Bt - x.At * dB_dPr) /
+                    ((1 + ratio2) * (1 + ratio2));
+    dFdT = dF_dFc * dFc_dT + dF_dPr * dPrdT;
+    dFdPr_over_F = dF_dPr / x.F;
+  } else if (r.blend == SRI) {
+    const auto& s = r.sri;
+    double e = s.size() > 4 ? s[4] : 0.0;
+    double lP = std::log10(x.Pr);
+    double dX_dPr = -x.Xs * x.Xs * 2 * lP / (x.Pr * kLn10);
+    double num = s[0] * s[1] / (T * T) * std::exp(-s[1] / T) - 1.0 / s[2] * std::exp(-T / s[2]);
+    dFdT = x.F * (e / T + x.Xs * num / x.sri_base + dX_dPr * dPrdT * std::log(x.sri_base));
+    dFdPr_over_F = dX_dPr * std::log(x.sri_base);
+  }
 }
 
 // ---------------------------------------------------------- analytical Jacobian (Sec. 3)
@@ -582,41 +631,7 @@ void jacobian(const Mech& m, double T, double p, const double* y, double* J /* N
     if (r.kind == FALLOFF || r.kind == CHEMACT) {
       dlnPrdT = (r.low.b - r.high.b + (r.low.Ta - r.high.Ta) / T - 1) / T;       // Eq. (dPridT) / P_r
       dPrdT = x.Pr * dlnPrdT;
-      if (x.Pr <= 0) {
-        // P_r -> 0+ limit (see reaction_values): F depends on T alone, and
-        // every P_r-derivative of ln F vanishes in the limit
-        if (r.blend == TROE) {
-          const auto& t = r.troe;
-          double dFc_dT = -(1 - t[0]) / t[1] * std::exp(-T / t[1]) - t[0] / t[2] * std::exp(-T / t[2]);
-          if (t.size() > 3) dFc_dT += t[3] / (T * T) * std::exp(-t[3] / T);
-          dFdT = x.F / (x.Fcent * (1 + 1 / (0.14 * 0.14))) * dFc_dT;
-        } else if (r.blend == SRI) {
-          dFdT = x.F * ((r.sri.size() > 4 ? r.sri[4] : 0.0) / T);
-        }
-      } else if (r.blend == TROE) {
-        const auto& t = r.troe;
-        double ratio2 = (x.At / x.Bt) * (x.At / x.Bt);
-        double dA_dFc = -0.67 / (x.Fcent * kLn10), dB_dFc = -1.1762 / (x.Fcent * kLn10);
-        double dA_dPr = 1.0 / (x.Pr * kLn10), dB_dPr = -0.14 / (x.Pr * kLn10);
-        double lnFc = std::log(x.Fcent);
-        double dF_dFc = x.F * (1.0 / (x.Fcent * (1 + ratio2)) -
-                               lnFc * 2 * x.At / (x.Bt * x.Bt * x.Bt) * (dA_dFc * x.Bt - x.At * dB_dFc) /
-                                   ((1 + ratio2) * (1 + ratio2)));
-        double dFc_dT = -(1 - t[0]) / t[1] * std::exp(-T / t[1]) - t[0] / t[2] * std::exp(-T / t[2]);
-        if (t.size() > 3) dFc_dT += t[3] / (T * T) * std::exp(-t[3] / T);
-        double dF_dPr = -x.F * lnFc * 2 * x.At / (x.Bt * x.Bt * x.Bt) * (dA_dPr * x.Bt - x.At * dB_dPr) /
-                        ((1 + ratio2) * (1 + ratio2));
-        dFdT = dF_dFc * dFc_dT + dF_dPr * dPrdT;
-        dFdPr_over_F = dF_dPr / x.F;
-      } else if (r.blend == SRI) {
-        const auto& s = r.sri;
-        double e = s.size() > 4 ? s[4] : 0.0;
-        double lP = std::log10(x.Pr);
-        double dX_dPr = -x.Xs * x.Xs * 2 * lP / (x.Pr * kLn10);
-        double num = s[0] * s[1] / (T * T) * std::exp(-s[1] / T) - 1.0 / s[2] * std::exp(-T / s[2]);
-        dFdT = x.F * (e / T + x.Xs * num / x.sri_base + dX_dPr * dPrdT * std::log(x.sri_base));
-        dFdPr_over_F = dX_dPr * std::log(x.sri_base);
-      }
+      blend_derivs(r, x, T, dPrdT, dFdT, dFdPr_over_F);
     }
     if (r.kind == THD) dcdT[i] = -x.c / T;
     else if (r.kind == FALLOFF) dcdT[i] = x.c * (dlnPrdT / (1 + x.Pr) + dFdT / x.F);
@@ -697,6 +712,217 @@ void jacobian(const Mech& m, double T, double p, const double* y, double* J /* N
   for (int k = 0; k < N - 1; ++k) {
     J[(size_t)(k + 1) * N] = JT[k];
     for (int j = 0; j < N - 1; ++j) J[(size_t)(k + 1) * N + j + 1] = JY[(size_t)k * (N - 1) + j];
+  }
+}
+
+// ------------------------------------- constant-volume, concentration-based form
+// State Phi_C = {T, [X_1], ..., [X_N]} of a constant-volume reactor: Sec. 3.3
+// names this formulation (concentrations as state variables, no density in
+// the cross-species elements) as the route to a sparse Jacobian, and Sec. 6
+// plans it.  The rate laws are those of Sec. 2.3 evaluated at p = R T sum [X_k]
+// (Eq. state); the ODE is
+//   d[X_k]/dt = wdot_k,
+//   dT/dt = -sum_k U_k wdot_k / sum_k [X_k] C_v,k,
+// with molar internal energies U_k = H_k - R T and heat capacities
+// C_v,k = C_p,k - R (Sec. 2.2 polynomials): energy conservation at constant
+// volume.  Its Jacobian is the plain definition J = d f / d Phi_C.
+
+template <class S> S make_state_conc(const Mech& m, const S& T, const S* C, State<S>& st) {
+  const int N = m.N;
+  st.N = N;
+  st.T = T;
+  st.X.assign(C, C + N);
+  st.Xre.resize(N);
+  for (int k = 0; k < N; ++k) st.Xre[k] = double(re(C[k]));
+  st.cpR.resize(N); st.hRT.resize(N); st.sR.resize(N);
+  thermo(m, T, st.cpR.data(), st.hRT.data(), st.sR.data());
+  S sum = S(0);
+  for (int k = 0; k < N; ++k) sum += C[k];
+  return S(kR) * T * sum;                                          // p, Eq. (state)
+}
+
+template <class S> void rhs_conc(const Mech& m, const S& T, const S* C, S* f /* N + 1 */) {
+  State<S> st;
+  const S p = make_state_conc(m, T, C, st);
+  const int N = m.N;
+  std::vector<S> q(m.NR);
+  RxnVals<S> v;
+  for (int i = 0; i < m.NR; ++i) {
+    reaction_values(m, i, st, p, v);
+    q[i] = v.c * (v.Rf - v.Rr);
+  }
+  S num = S(0), den = S(0);
+  for (int k = 0; k < N; ++k) {
+    S w = S(0);
+    for (int i : m.species_rxns[k]) w += S(m.nu(k, i)) * q[i];
+    f[k + 1] = w;
+    const S U = S(kR) * T * (st.hRT[k] - S(1));                   // molar internal energy
+    const S Cv = S(kR) * (st.cpR[k] - S(1));                      // molar C_v
+    num += U * w;
+    den += C[k] * Cv;
+  }
+  f[0] = -num / den;
+}
+
+// d ln k_f / dT at fixed p and d ln k_f / d ln p of the forward rate coefficient
+// (Sec. 2.3 Arrhenius, Sec. 2.3.4 PLOG and Chebyshev).  PLOG: ln k is linear in
+// ln p inside a bracket (the last grid point p_n <= p), flat outside the grid;
+// Chebyshev: d log10 k / d log10 p from the U-polynomial derivative of T_b.
+void kf_log_derivs(const Rxn& r, double T, double p, double& dlnk_dT, double& dlnk_dlnp) {
+  dlnk_dlnp = 0;
+  switch (r.kind) {
+    case ELEM: case THD: dlnk_dT = (r.arr.b + r.arr.Ta / T) / T; break;
+    case FALLOFF: dlnk_dT = (r.high.b + r.high.Ta / T) / T; break;
+    case CHEMACT: dlnk_dT = (r.low.b + r.low.Ta / T) / T; break;
+    case PLOG: {
+      const auto& pts = r.plog;
+      const int n = (int)pts.size();
+      auto lnk = [&](int q) { return std::log(pts[q][1]) + pts[q][2] * std::log(T) - pts[q][3] / T; };
+      auto dlnk = [&](int q) { return (pts[q][2] + pts[q][3] / T) / T; };
+      if (n == 1 || p <= pts[0][0]) dlnk_dT = dlnk(0);
+      else if (p >= pts[n - 1][0]) dlnk_dT = dlnk(n - 1);
+      else {
+        int lo = 0;
+        for (int q = 0; q < n - 1; ++q) if (pts[q][0] <= p) lo = q;
+        const double w = (std::log(p) - std::log(pts[lo][0])) / (std::log(pts[lo + 1][0]) - std::log(pts[lo][0]));
+        dlnk_dT = dlnk(lo) + (dlnk(lo + 1) - dlnk(lo)) * w;
+        dlnk_dlnp = (lnk(lo + 1) - lnk(lo)) / (std::log(pts[lo + 1][0]) - std::log(pts[lo][0]));
+      }
+      break;
+    }
+    case CHEB: {
+      const double span_T = 1 / r.Tmax - 1 / r.Tmin, span_p = std::log10(r.Pmax) - std::log10(r.Pmin);
+      const double Tr = (2 / T - 1 / r.Tmin - 1 / r.Tmax) / span_T;
+      const double pr = (2 * std::log10(p) - std::log10(r.Pmin) - std::log10(r.Pmax)) / span_p;
+      std::vector<double> tT(r.nT), uT(r.nT), tP(r.nP), uP(r.nP);
+      cheb_polys(r.nT, Tr, tT.data(), uT.data());
+      cheb_polys(r.nP, pr, tP.data(), uP.data());
+      double dT_sum = 0, dp_sum = 0;
+      for (int a = 0; a < r.nT; ++a)
+        for (int b = 0; b < r.nP; ++b) {
+          const double eta = r.eta[a * r.nP + b];
+          if (a > 0) dT_sum += eta * a * uT[a - 1] * tP[b];           // dT_a/dx = a U_{a-1}
+          if (b > 0) dp_sum += eta * tT[a] * b * uP[b - 1];
+        }
+      dlnk_dT = kLn10 * dT_sum * (-2 / (T * T)) / span_T;
+      dlnk_dlnp = dp_sum * 2 / span_p;                           // d log10 k / d log10 p
+      break;
+    }
+  }
+}
+
+// J = d f / d Phi_C, (N+1) x (N+1) row-major: row 0 and column 0 are T, row and
+// column k+1 the concentration of species k.  Element by element: per-reaction
+// derivative vectors dq_i/dT and dq_i/d[X_j] from the product and chain rules,
+// then each species row summed over its reactions, then the temperature row.
+void jacobian_conc(const Mech& m, double T, const double* C, double* J) {
+  const int N = m.N, NR = m.NR, N1 = N + 1;
+  State<double> st;
+  const double p = make_state_conc(m, T, C, st);
+  double Msum = 0;
+  for (int k = 0; k < N; ++k) Msum += C[k];
+  // d ln p / dT = 1/T and d ln p / d[X_j] = 1/sum[X] at constant volume
+  std::vector<double> dBdT(N);
+  for (int k = 0; k < N; ++k) {
+    const auto& a = (T <= m.tmid[k]) ? m.lo[k] : m.hi[k];
+    dBdT[k] = (a[0] - 1 + a[5] / T) / T + a[1] / 2 + T * (a[2] / 3 + T * (a[3] / 4 + a[4] / 5 * T));
+  }
+  std::vector<double> dqdT(NR), dqdC((size_t)NR * N, 0.0), q(NR);
+  for (int i = 0; i < NR; ++i) {
+    const Rxn& r = m.rxn[i];
+    RxnVals<double> x;
+    reaction_values(m, i, st, p, x);
+    q[i] = x.c * (x.Rf - x.Rr);
+    double dlnkf_dT = 0, dlnkf_dlnp = 0;
+    kf_log_derivs(r, T, p, dlnkf_dT, dlnkf_dlnp);
+    const double dlnkf_dT_C = dlnkf_dT + dlnkf_dlnp / T;           // along constant concentrations
+    double dkr_dT = 0, dkr_dlnp = 0;
+    if (r.rev == KC) {
+      double snu = 0;
+      for (int k : m.rxn_species[i]) { int n = m.nu(k, i); if (n) snu += n * dBdT[k]; }
+      dkr_dT = x.kr * (dlnkf_dT_C - snu);                            // K_c depends on T only
+      dkr_dlnp = x.kr * dlnkf_dlnp;
+    } else if (r.rev == EXPLICIT) {
+      dkr_dT = x.kr * (r.revarr.b + r.revarr.Ta / T) / T;
+    }
+    double pf = 1, pr = 1;
+    for (auto& [k, n] : r.reac) pf *= ipow(C[k], n);
+    for (auto& [k, n] : r.prod) pr *= ipow(C[k], n);
+    const double dRf_dT = x.kf * dlnkf_dT_C * pf, dRr_dT = dkr_dT * pr;
+    // pressure modification
+    double dcdT = 0, dPrdT = 0, dFdT = 0, dFdPr_over_F = 0;
+    if (r.kind == FALLOFF || r.kind == CHEMACT) {
+      const double dlnPrdT = (r.low.b - r.high.b + (r.low.Ta - r.high.Ta) / T) / T;   // [X]_i fixed
+      dPrdT = x.Pr * dlnPrdT;
+      blend_derivs(r, x, T, dPrdT, dFdT, dFdPr_over_F);
+      if (r.kind == FALLOFF) dcdT = x.c * (dlnPrdT / (1 + x.Pr) + dFdT / x.F);
+      else dcdT = x.c * (-dPrdT / (1 + x.Pr) + dFdT / x.F);
+    }
+    dqdT[i] = dcdT * (x.Rf - x.Rr) + x.c * (dRf_dT - dRr_dT);
+    double* dq = &dqdC[(size_t)i * N];
+    for (int j = 0; j < N; ++j) {
+      // d[X]_i / d[X_j]
+      double dE = 0;
+      if (r.kind == THD || r.kind == FALLOFF || r.kind == CHEMACT)
+        dE = r.collider_species ? (j == r.m ? 1.0 : 0.0) : r.alpha[j];
+      double dc = 0;
+      if (r.kind == THD) dc = dE;
+      else if (r.kind == FALLOFF || r.kind == CHEMACT) {
+        const double dPr = x.k0 / x.kinf * dE;
+        if (r.kind == FALLOFF) dc = x.F / ((1 + x.Pr) * (1 + x.Pr)) * dPr + x.c * dFdPr_over_F * dPr;
+        else dc = x.c * (-dPr / (1 + x.Pr) + dFdPr_over_F * dPr);
+      }
+      // dR/d[X_j]: mass-action product rule plus the pressure dependence of k
+      double dpf = 0, dpr = 0;
+      for (auto& [k, n] : r.reac)
+        if (k == j) {
+          double other = 1;
+          for (auto& [l, nl] : r.reac) if (l != k) other *= ipow(C[l], nl);
+          dpf = n * ipow(C[k], n - 1) * other;
+        }
+      for (auto& [k, n] : r.prod)
+        if (k == j) {
+          double other = 1;
+          for (auto& [l, nl] : r.prod) if (l != k) other *= ipow(C[l], nl);
+          dpr = n * ipow(C[k], n - 1) * other;
+        }
+      const double dRf = x.kf * dlnkf_dlnp / Msum * pf + x.kf * dpf;
+      const double dRr = dkr_dlnp / Msum * pr + x.kr * dpr;
+      dq[j] = dc * (x.Rf - x.Rr) + x.c * (dRf - dRr);
+    }
+  }
+  std::vector<double> wdot(N, 0.0), U(N), Cv(N), dCv(N);
+  for (int k = 0; k < N; ++k) {
+    for (int i : m.species_rxns[k]) wdot[k] += m.nu(k, i) * q[i];
+    const auto& a = (T <= m.tmid[k]) ? m.lo[k] : m.hi[k];
+    U[k] = kR * T * (st.hRT[k] - 1);
+    Cv[k] = kR * (st.cpR[k] - 1);
+    dCv[k] = kR * (a[1] + T * (2 * a[2] + T * (3 * a[3] + 4 * a[4] * T)));
+  }
+  // species rows
+  for (int k = 0; k < N; ++k) {
+    double acc = 0;
+    for (int i : m.species_rxns[k]) acc += m.nu(k, i) * dqdT[i];
+    J[(size_t)(k + 1) * N1] = acc;
+    for (int j = 0; j < N; ++j) {
+      double s = 0;
+      for (int i : m.species_rxns[k]) s += m.nu(k, i) * dqdC[(size_t)i * N + j];
+      J[(size_t)(k + 1) * N1 + j + 1] = s;
+    }
+  }
+  // temperature row: f_0 = -num / den, num = sum U_k wdot_k, den = sum [X_k] C_v,k;
+  // dU_k/dT = C_v,k
+  double num = 0, den = 0, dden_dT = 0;
+  for (int k = 0; k < N; ++k) { num += U[k] * wdot[k]; den += C[k] * Cv[k]; dden_dT += C[k] * dCv[k]; }
+  {
+    double dnum = 0;
+    for (int k = 0; k < N; ++k) dnum += Cv[k] * wdot[k] + U[k] * J[(size_t)(k + 1) * N1];
+    J[0] = -dnum / den + num * dden_dT / (den * den);
+  }
+  for (int j = 0; j < N; ++j) {
+    double dnum = 0;
+    for (int k = 0; k < N; ++k) dnum += U[k] * J[(size_t)(k + 1) * N1 + j + 1];
+    J[j + 1] = -dnum / den + num * Cv[j] / (den * den);
   }
 }
 
@@ -813,6 +1039,55 @@ int pyjac_ref_eval_jacobian_cs(void* h, int64_t n, int64_t ld, const double* phi
       for (int j = 0; j < N - 1; ++j) y[j] = C(phi[(j + 1) * ld + s], (col == j + 1) ? step : 0.0);
       rhs<C>(m, T, p[s], y.data(), w.data(), f.data(), nullptr, nullptr, nullptr);
       for (int row = 0; row < N; ++row) jac[((size_t)row * N + col) * ld + s] = f[row].imag() / step;
+    }
+  }
+  return 0;
+}
+
+// Constant-volume, concentration-based form: phi_c [(N+1)][ld] holds T and
+// [X_1..X_N]; f [(N+1)][ld]; jac [(N+1)^2][ld] row-major per state.
+int pyjac_ref_eval_rhs_conc(void* h, int64_t n, int64_t ld, const double* phi_c, double* f, int nthreads) {
+  if (!h || !phi_c || !f || n < 0 || ld < n) { g_err = "bad argument"; return -1; }
+  const Mech& m = *as_mech(h);
+  const int N1 = m.N + 1;
+#pragma omp parallel for schedule(dynamic, 8) num_threads(nthreads_or_default(nthreads))
+  for (int64_t s = 0; s < n; ++s) {
+    std::vector<double> C(m.N), out(N1);
+    for (int k = 0; k < m.N; ++k) C[k] = phi_c[(k + 1) * ld + s];
+    rhs_conc<double>(m, phi_c[s], C.data(), out.data());
+    for (int e = 0; e < N1; ++e) f[e * ld + s] = out[e];
+  }
+  return 0;
+}
+
+int pyjac_ref_eval_jacobian_conc(void* h, int64_t n, int64_t ld, const double* phi_c, double* jac, int nthreads) {
+  if (!h || !phi_c || !jac || n < 0 || ld < n) { g_err = "bad argument"; return -1; }
+  const Mech& m = *as_mech(h);
+  const size_t N1 = m.N + 1;
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads_or_default(nthreads))
+  for (int64_t s = 0; s < n; ++s) {
+    std::vector<double> C(m.N), J(N1 * N1);
+    for (int k = 0; k < m.N; ++k) C[k] = phi_c[(k + 1) * ld + s];
+    jacobian_conc(m, phi_c[s], C.data(), J.data());
+    for (size_t e = 0; e < N1 * N1; ++e) jac[e * ld + s] = J[e];
+  }
+  return 0;
+}
+
+int pyjac_ref_eval_jacobian_conc_cs(void* h, int64_t n, int64_t ld, const double* phi_c, double* jac, double step,
+                                    int nthreads) {
+  if (!h || !phi_c || !jac || n < 0 || ld < n || !(step > 0)) { g_err = "bad argument"; return -1; }
+  const Mech& m = *as_mech(h);
+  const int N1 = m.N + 1;
+  using Cx = std::complex<double>;
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads_or_default(nthreads))
+  for (int64_t s = 0; s < n; ++s) {
+    std::vector<Cx> C(m.N), f(N1);
+    for (int col = 0; col < N1; ++col) {
+      Cx T(phi_c[s], col == 0 ? step : 0.0);
+      for (int k = 0; k < m.N; ++k) C[k] = Cx(phi_c[(k + 1) * ld + s], (col == k + 1) ? step : 0.0);
+      rhs_conc<Cx>(m, T, C.data(), f.data());
+      for (int row = 0; row < N1; ++row) jac[((size_t)row * N1 + col) * ld + s] = f[row].imag() / step;
     }
   }
   return 0;

@@ -47,6 +47,9 @@ def _load():
         lib.pyjac_ref_eval_rhs_ld.argtypes = [vp, i64, i64, dp, dp, dp, i32]
         lib.pyjac_ref_eval_jacobian.argtypes = [vp, i64, i64, dp, dp, dp, i32]
         lib.pyjac_ref_eval_jacobian_cs.argtypes = [vp, i64, i64, dp, dp, dp, ctypes.c_double, i32]
+        lib.pyjac_ref_eval_rhs_conc.argtypes = [vp, i64, i64, dp, dp, i32]
+        lib.pyjac_ref_eval_jacobian_conc.argtypes = [vp, i64, i64, dp, dp, i32]
+        lib.pyjac_ref_eval_jacobian_conc_cs.argtypes = [vp, i64, i64, dp, dp, ctypes.c_double, i32]
         lib.pyjac_ref_species_thermo.argtypes = [vp, ctypes.c_double, dp, dp, dp]
         lib.pyjac_ref_reaction_terms.argtypes = [vp, ctypes.c_double, ctypes.c_double, dp,
                                                  dp, dp, dp, dp, dp, dp, dp, dp]
@@ -123,6 +126,31 @@ class RefMech:
         jac = np.empty((self.n_species ** 2, n))
         self._chk(_lib.pyjac_ref_eval_jacobian_cs(self._h, n, n, _ptr(phi), _ptr(p), _ptr(jac),
                                                   step, nthreads))
+        return jac
+
+    # constant-volume, concentration-based form: phi_c is (N+1, n) with rows
+    # T, [X_1], ..., [X_N]
+    def eval_rhs_conc(self, phi_c, nthreads: int = 0):
+        phi_c = _f64(phi_c)
+        n = phi_c.shape[1]
+        f = np.empty((self.n_species + 1, n))
+        self._chk(_lib.pyjac_ref_eval_rhs_conc(self._h, n, n, _ptr(phi_c), _ptr(f), nthreads))
+        return f
+
+    def eval_jacobian_conc(self, phi_c, nthreads: int = 0):
+        """Analytical Jacobian of the concentration form, shape ((N+1)^2, n)."""
+        phi_c = _f64(phi_c)
+        n = phi_c.shape[1]
+        jac = np.empty(((self.n_species + 1) ** 2, n))
+        self._chk(_lib.pyjac_ref_eval_jacobian_conc(self._h, n, n, _ptr(phi_c), _ptr(jac), nthreads))
+        return jac
+
+    def eval_jacobian_conc_cs(self, phi_c, step: float = 1e-30, nthreads: int = 0):
+        phi_c = _f64(phi_c)
+        n = phi_c.shape[1]
+        jac = np.empty(((self.n_species + 1) ** 2, n))
+        self._chk(_lib.pyjac_ref_eval_jacobian_conc_cs(self._h, n, n, _ptr(phi_c), _ptr(jac), step,
+                                                       nthreads))
         return jac
 
     def species_thermo(self, T: float):
