@@ -133,6 +133,35 @@ pyjac_status pyjac_eval_rates(const pyjac_mech* mech, int64_t n_states, int64_t 
 pyjac_status pyjac_eval_jacobian(const pyjac_mech* mech, int64_t n_states, int64_t ld,
                                  const double* phi, const double* p, double* jac, void* stream);
 
+/* Sparse Jacobian of the concentration-based, constant-volume formulation
+ * that Sec. 3.3 names as the route to Jacobian sparsity (concentrations as
+ * state variables remove the density from the cross-species elements) and
+ * Sec. 6 plans.  State per state s: phi_c[(N+1)][ld] = {T, [X_1], ..., [X_N]}
+ * (K, kmol/m^3), constant volume, p = R T sum [X_k] (Eq. state) in the PLOG
+ * and Chebyshev rates; the ODE is d[X_k]/dt = wdot_k (Sec. 2.3 rate laws) and
+ * dT/dt = -sum_k U_k wdot_k / sum_k [X_k] C_v,k with molar U_k = H_k - R T,
+ * C_v,k = C_p,k - R (Sec. 2.2 polynomials).  The species block is stored as a
+ * dense vector u plus a sparse matrix S with the fixed compressed-column
+ * pattern of pyjac_conc_pattern: J_{k,j} = u_k + S_{k,j} (u collects the
+ * all-species third-body baseline and the pressure dependence; S the
+ * mass-action and non-unit-efficiency terms).  jac[(3N+1+nnz)][ld]:
+ *   e = 0            d(dT/dt)/dT
+ *   e = 1 .. N       d wdot_k/dT,            k = e - 1
+ *   e = N+1 .. 2N    d(dT/dt)/d[X_j],        j = e - N - 1
+ *   e = 2N+1 .. 3N   u_k,                     k = e - 2N - 1
+ *   e = 3N+1 + q     S value q: column j holds q in [colptr[j], colptr[j+1]),
+ *                    row rowidx[q] (ascending within a column)
+ * Errors: PYJAC_E_INVALID (NULL arrays, n < 0, ld < n, misaligned, wrong
+ * device), PYJAC_E_UNSUPPORTED (mechanism too large for the tile),
+ * PYJAC_E_DEVICE.  n_states == 0 is a no-op. */
+pyjac_status pyjac_eval_jacobian_conc(const pyjac_mech* mech, int64_t n_states, int64_t ld,
+                                      const double* phi_c, double* jac, void* stream);
+
+/* Host copy of the compressed-column pattern of S above: colptr[N+1] and
+ * rowidx[nnz] (either may be NULL; *nnz, if given, receives nnz).  Caller-owned
+ * host arrays. */
+pyjac_status pyjac_conc_pattern(const pyjac_mech* mech, int32_t* colptr, int32_t* rowidx, int64_t* nnz);
+
 /* Finite-difference Jacobian: the first-order forward-difference
  * approximation the paper measures the analytical Jacobian against (Sec. 5,
  * finite differences as in CVODE).  Column j of state s is
@@ -242,7 +271,8 @@ pyjac_status pyjac_newton_factor_solve_noalloc(const pyjac_mech* mech, int64_t n
                                                void* stream);
 
 /* Tuning: force the launch shape of one kernel family of this handle
- * (which = 0: rates kernel, 1: Jacobian kernel) to tile_states states per
+ * (which = 0: rates kernel, 1: Jacobian kernel, 2: concentration-form
+ * Jacobian) to tile_states states per
  * workgroup and `threads` threads per workgroup; tile_states = 0 restores the
  * automatic choice (largest tile whose LDS working set fits the device).
  * Results per state do not depend on the shape (all per-state sums run in
@@ -253,10 +283,12 @@ pyjac_status pyjac_mech_set_variant(pyjac_mech* mech, int32_t which, int32_t til
                                     int32_t threads);
 
 /* Autotuner: times every compiled launch shape of one kernel family
- * (which = 0: rates kernel writing the RHS only, 1: Jacobian kernel) that fits
- * the device and the mechanism, on the caller's own batch (n_states states of
- * phi[N][ld], p[ld], output written to out: [N][ld] doubles for which = 0,
- * [N*N][ld] for which = 1), `reps` timed launches each after one warm-up,
+ * (which = 0: rates kernel writing the RHS only, 1: Jacobian kernel, 2:
+ * concentration-form Jacobian) that fits the device and the mechanism, on the
+ * caller's own batch (n_states states of phi[N][ld], p[ld], output written to
+ * out: [N][ld] doubles for which = 0, [N*N][ld] for which = 1; for which = 2
+ * phi is phi_c[(N+1)][ld], p is ignored (may be NULL) and out holds
+ * [(3N+1+nnz)][ld]), `reps` timed launches each after one warm-up,
  * and keeps the fastest median for this handle (a shape later in the
  * preference order must be at least 2 % faster to win).  Every launch is ordered on
  * `stream` and the call returns after the last one has finished.  Optional

@@ -113,6 +113,30 @@ class Mechanism:
                                  self._stream())
         return out
 
+    def conc_pattern(self):
+        """Compressed-column pattern (colptr [N+1], rowidx [nnz]) of the sparse
+        part of the concentration-form Jacobian."""
+        if getattr(self, "_conc_pattern", None) is None:
+            self._conc_pattern = _lib.pyjac_conc_pattern(self._h)
+        return self._conc_pattern
+
+    def eval_jacobian_conc(self, phi_c, out=None):
+        """Concentration-based, constant-volume Jacobian for phi_c [N+1, n]
+        (rows T, [X_1..X_N]); returns [3N+1+nnz, ld] (layout in pyjac.h)."""
+        torch = _torch()
+        N = self.n_species
+        if phi_c.dtype != torch.float64 or not phi_c.is_cuda or phi_c.dim() != 2 or phi_c.shape[0] != N + 1 \
+                or phi_c.stride(1) != 1:
+            raise ValueError("phi_c must be a float64 GPU tensor [N+1, n] with unit state stride")
+        n, ld = phi_c.shape[1], phi_c.stride(0)
+        rows = 3 * N + 1 + len(self.conc_pattern()[1])
+        if out is None:
+            out = torch.empty((rows, ld), dtype=torch.float64, device=phi_c.device)
+        elif out.shape[0] != rows or out.stride(0) != ld or out.stride(1) != 1:
+            raise ValueError(f"out must be [{rows}, ld] with the same ld as phi_c")
+        _lib.pyjac_eval_jacobian_conc(self._h, n, ld, phi_c.data_ptr(), out.data_ptr(), self._stream())
+        return out
+
     def eval_jacobian_fd(self, phi, p, out=None, chunk_states: int = 8192, workspace=None):
         """Forward-difference Jacobian (same layout as eval_jacobian)."""
         torch = _torch()
@@ -184,11 +208,17 @@ class Mechanism:
 
     def autotune(self, which: int, phi, p, out=None, reps: int = 3):
         """Time every launch shape of kernel family `which` (0 rates, 1
-        Jacobian) on this batch and keep the fastest; returns
+        Jacobian, 2 concentration-form Jacobian: phi is phi_c [N+1, n], p is
+        ignored) on this batch and keep the fastest; returns
         [((tile_states, threads), median ms), ...]."""
         torch = _torch()
-        n, ld = self._check_in(phi, p)
-        rows = self.n_species * (self.n_species if which == 1 else 1)
+        if which == 2:
+            n, ld = phi.shape[1], phi.stride(0)
+            p = phi
+            rows = 3 * self.n_species + 1 + len(self.conc_pattern()[1])
+        else:
+            n, ld = self._check_in(phi, p)
+            rows = self.n_species * (self.n_species if which == 1 else 1)
         if out is None:
             out = torch.empty((rows, ld), dtype=torch.float64, device=phi.device)
         elif out.shape[0] != rows or out.stride(0) != ld or out.stride(1) != 1:

@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "PYJAC_OK", -1: "PYJAC_E_INVALID", -2: "PYJAC_E_PARSE",
 # Every symbol include/pyjac.h declares.
 EXPORTED = ("pyjac_mech_load", "pyjac_mech_load_string", "pyjac_chemkin_to_text",
             "pyjac_mech_load_chemkin", "pyjac_mech_info", "pyjac_mech_free",
-            "pyjac_eval_rates", "pyjac_eval_jacobian", "pyjac_newton_workspace_bytes",
+            "pyjac_eval_rates", "pyjac_eval_jacobian", "pyjac_eval_jacobian_conc", "pyjac_conc_pattern",
+            "pyjac_newton_workspace_bytes",
             "pyjac_newton_factor_solve", "pyjac_newton_factor_solve_noalloc", "pyjac_mech_set_variant", "pyjac_mech_get_variant",
             "pyjac_mech_autotune", "pyjac_fd_workspace_bytes", "pyjac_eval_jacobian_fd",
             "pyjac_sdirk3_workspace_bytes", "pyjac_sdirk3_step",
@@ -66,6 +67,10 @@ def load_library() -> ctypes.CDLL:
     lib.pyjac_eval_rates.restype = st
     lib.pyjac_eval_jacobian.argtypes = [vp, i64, i64, vp, vp, vp, vp]
     lib.pyjac_eval_jacobian.restype = st
+    lib.pyjac_eval_jacobian_conc.argtypes = [vp, i64, i64, vp, vp, vp]
+    lib.pyjac_eval_jacobian_conc.restype = st
+    lib.pyjac_conc_pattern.argtypes = [vp, vp, vp, ctypes.POINTER(i64)]
+    lib.pyjac_conc_pattern.restype = st
     lib.pyjac_newton_workspace_bytes.argtypes = [vp, i64, i32]
     lib.pyjac_newton_workspace_bytes.restype = sz
     lib.pyjac_newton_factor_solve.argtypes = [vp, i64, i64, vp, vp, ctypes.c_double, vp, vp, i32,
@@ -168,6 +173,24 @@ def pyjac_eval_rates(mech, n, ld, phi, p, rop_f, rop_r, pres_mod, wdot, dphi, st
 
 def pyjac_eval_jacobian(mech, n, ld, phi, p, jac, stream) -> None:
     check(load_library().pyjac_eval_jacobian(mech, n, ld, phi, p, jac, stream), "pyjac_eval_jacobian")
+
+
+def pyjac_eval_jacobian_conc(mech, n, ld, phi_c, jac, stream) -> None:
+    check(load_library().pyjac_eval_jacobian_conc(mech, n, ld, phi_c, jac, stream), "pyjac_eval_jacobian_conc")
+
+
+def pyjac_conc_pattern(mech):
+    """(colptr [N+1], rowidx [nnz]) as int32 numpy arrays."""
+    import numpy as np
+    lib = load_library()
+    nnz = ctypes.c_int64()
+    check(lib.pyjac_conc_pattern(mech, None, None, ctypes.byref(nnz)), "pyjac_conc_pattern")
+    ns = ctypes.c_int32()
+    check(lib.pyjac_mech_info(mech, ctypes.byref(ns), None, None), "pyjac_mech_info")
+    colptr = np.empty(ns.value + 1, dtype=np.int32)
+    rowidx = np.empty(max(nnz.value, 1), dtype=np.int32)
+    check(lib.pyjac_conc_pattern(mech, colptr.ctypes.data, rowidx.ctypes.data, None), "pyjac_conc_pattern")
+    return colptr, rowidx[: nnz.value]
 
 
 def pyjac_newton_workspace_bytes(mech, n, mode) -> int:

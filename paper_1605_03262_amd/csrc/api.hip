@@ -18,6 +18,9 @@
 namespace pyjac {
 
 size_t tile_lds_bytes(int N, int NR, int NG, int TS, int NT, bool jac);
+size_t conc_lds_bytes(int N, int NR, int NG, int TS, int NT);
+hipError_t launch_conc(int TS, int NT, const MechDev& md, int64_t n, int64_t ld, const double* phi, double* out,
+                       size_t lds, hipStream_t st);
 hipError_t launch_tile(bool jac_mode, int TS, int NT, const MechDev& md, int64_t n, int64_t ld,
                        const double* phi, const double* p, double* rop_f, double* rop_r, double* pmod,
                        double* wdot, double* dphi, double* jac, size_t lds, hipStream_t st);
@@ -45,7 +48,7 @@ struct pyjac_mech {
   void* dmem = nullptr;
   int device = 0;
   size_t max_lds = 65536;
-  pyjac::Variant jac_var, rates_var;
+  pyjac::Variant jac_var, rates_var, conc_var;
   // per launch shape: species-list chunk bounds, built when the shape is chosen
   struct VarDev {
     int ts = 0, nt = 0;
@@ -85,6 +88,25 @@ Variant pick(const PackedMech& P, bool jac, size_t max_lds) {
   return {0, 0};
 }
 
+// Shapes compiled for the concentration-form Jacobian, most preferred first.
+const int kConcShapes[][2] = {{16, 1024}, {8, 1024}, {8, 512}, {4, 1024}, {4, 512}, {2, 512}};
+
+bool conc_fits(const PackedMech& P, Variant v, size_t max_lds) {
+  return kpt_of(P.N, v.ts, v.nt) <= 8 && conc_lds_bytes(P.N, P.NR, P.NG, v.ts, v.nt) <= max_lds;
+}
+
+Variant pick_conc(const PackedMech& P, size_t max_lds) {
+  for (auto& q : kConcShapes)
+    if (conc_fits(P, Variant{q[0], q[1]}, max_lds)) return {q[0], q[1]};
+  return {0, 0};
+}
+
+size_t kind_lds(const pyjac_mech* m, int which, Variant v) {
+  const PackedMech& P = m->host;
+  return which == 2 ? conc_lds_bytes(P.N, P.NR, P.NG, v.ts, v.nt)
+                    : tile_lds_bytes(P.N, P.NR, P.NG, v.ts, v.nt, which == 1);
+}
+
 pyjac_status upload(pyjac_mech* m) {
   PackedMech& P = m->host;
   std::vector<char> blob;
@@ -96,6 +118,8 @@ pyjac_status upload(pyjac_mech* m) {
   append(blob, P.spg_ent, o);
   append(blob, P.col_start, o); append(blob, P.colrec, o); append(blob, P.col_order, o);
   append(blob, P.col_flags, o);
+  append(blob, P.cv_col_start, o); append(blob, P.cv_colrec, o); append(blob, P.cv_col_order, o);
+  append(blob, P.cv_colptr, o);
   if (hipMalloc(&m->dmem, blob.size()) != hipSuccess) return fail(PYJAC_E_NOMEM, "hipMalloc of mechanism tables failed");
   if (hipMemcpy(m->dmem, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess)
     return fail(PYJAC_E_DEVICE, "copy of mechanism tables failed");
@@ -112,6 +136,8 @@ pyjac_status upload(pyjac_mech* m) {
   d.spg_ent = D((const int*)0);
   d.col_start = D((const int*)0); d.colrec = D((const ColRec*)0); d.col_order = D((const int*)0);
   d.col_flags = D((const uint32_t*)0);
+  d.cv_col_start = D((const int*)0); d.cv_colrec = D((const ColRec*)0); d.cv_col_order = D((const int*)0);
+  d.cv_colptr = D((const int*)0);
   d.spg_chunk = nullptr;
   return PYJAC_OK;
 }
@@ -201,8 +227,10 @@ pyjac_status pyjac_mech_load_string(const char* text, int32_t hip_device, pyjac_
     delete m;
     return fail(PYJAC_E_UNSUPPORTED, "mechanism too large for the per-tile LDS budget");
   }
+  m->conc_var = pick_conc(m->host, m->max_lds);   // {0, 0}: the concentration form does not fit
   rc = ensure_var(m, m->jac_var, true);
   if (rc == PYJAC_OK) rc = ensure_var(m, m->rates_var, false);
+  if (rc == PYJAC_OK && m->conc_var.ts) rc = ensure_var(m, m->conc_var, true);
   if (rc != PYJAC_OK) {
     pyjac_mech_free(m);
     return rc;
@@ -311,6 +339,37 @@ pyjac_status pyjac_eval_jacobian(const pyjac_mech* m, int64_t n, int64_t ld, con
   return PYJAC_OK;
 }
 
+pyjac_status pyjac_conc_pattern(const pyjac_mech* m, int32_t* colptr, int32_t* rowidx, int64_t* nnz) {
+  if (!m) return fail(PYJAC_E_INVALID, "mechanism handle is NULL");
+  const PackedMech& P = m->host;
+  if (nnz) *nnz = (int64_t)P.cv_rowidx.size();
+  if (colptr) std::memcpy(colptr, P.cv_colptr.data(), P.cv_colptr.size() * sizeof(int32_t));
+  if (rowidx && !P.cv_rowidx.empty())
+    std::memcpy(rowidx, P.cv_rowidx.data(), P.cv_rowidx.size() * sizeof(int32_t));
+  return PYJAC_OK;
+}
+
+pyjac_status pyjac_eval_jacobian_conc(const pyjac_mech* m, int64_t n, int64_t ld, const double* phi_c, double* jac,
+                                      void* stream) {
+  if (!m) return fail(PYJAC_E_INVALID, "mechanism handle is NULL");
+  if (n < 0) return fail(PYJAC_E_INVALID, "n_states is negative");
+  if (ld < n) return fail(PYJAC_E_INVALID, "ld is smaller than n_states");
+  if (n == 0) return PYJAC_OK;
+  if (!phi_c || !jac) return fail(PYJAC_E_INVALID, "phi_c and jac are required");
+  if (misaligned(phi_c) || misaligned(jac)) return fail(PYJAC_E_INVALID, "pointer not 8-byte aligned");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != m->device)
+    return fail(PYJAC_E_INVALID, "current HIP device differs from the mechanism's device");
+  if (ld > (int64_t)1 << 40) return fail(PYJAC_E_INVALID, "ld too large");
+  const Variant v = m->conc_var;
+  if (!v.ts) return fail(PYJAC_E_UNSUPPORTED, "mechanism too large for the concentration-form tile");
+  const size_t lds = conc_lds_bytes(m->host.N, m->host.NR, m->host.NG, v.ts, v.nt);
+  const MechDev md = launch_view(m, v, true);
+  hipError_t e = launch_conc(v.ts, v.nt, md, n, ld, phi_c, jac, lds, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("jacobian launch failed: ") + hipGetErrorString(e));
+  return PYJAC_OK;
+}
+
 size_t pyjac_fd_workspace_bytes(const pyjac_mech* m, int64_t chunk_states) {
   if (!m || chunk_states < 1) return 0;
   return (size_t)chunk_states * fd_bytes_per_state(m->host.N) + 1024;
@@ -356,7 +415,23 @@ pyjac_status pyjac_eval_jacobian_fd(const pyjac_mech* m, int64_t n, int64_t ld, 
 // 1 Jacobian).  ts = 0 restores the automatic choice.  Returns
 // PYJAC_E_UNSUPPORTED when the shape does not fit the device or the mechanism.
 pyjac_status pyjac_mech_set_variant(pyjac_mech* m, int32_t which, int32_t ts, int32_t nt) {
-  if (!m || (which != 0 && which != 1)) return fail(PYJAC_E_INVALID, "bad handle or kernel id");
+  if (!m || which < 0 || which > 2) return fail(PYJAC_E_INVALID, "bad handle or kernel id");
+  if (which == 2) {
+    Variant v{ts, nt};
+    if (ts == 0) v = pick_conc(m->host, m->max_lds);
+    else {
+      bool found = false;
+      for (auto& q : kConcShapes) found |= (q[0] == ts && q[1] == nt);
+      if (!found) return fail(PYJAC_E_UNSUPPORTED, "variant not compiled");
+      if (!conc_fits(m->host, v, m->max_lds)) return fail(PYJAC_E_UNSUPPORTED, "variant does not fit");
+    }
+    if (v.ts) {
+      pyjac_status rc = ensure_var(m, v, true);
+      if (rc != PYJAC_OK) return rc;
+    }
+    m->conc_var = v;
+    return PYJAC_OK;
+  }
   const bool jac = which == 1;
   Variant v{ts, nt};
   if (ts == 0) v = pick(m->host, jac, m->max_lds);
@@ -379,9 +454,10 @@ pyjac_status pyjac_mech_set_variant(pyjac_mech* m, int32_t which, int32_t ts, in
 pyjac_status pyjac_mech_autotune(pyjac_mech* m, int32_t which, int64_t n, int64_t ld, const double* phi,
                                  const double* p, double* out, int32_t reps, int32_t* shapes, float* ms,
                                  int32_t max_entries, int32_t* n_entries, void* stream) {
-  if (!m || (which != 0 && which != 1)) return fail(PYJAC_E_INVALID, "bad handle or kernel id");
+  if (!m || which < 0 || which > 2) return fail(PYJAC_E_INVALID, "bad handle or kernel id");
   if (reps < 1 || n < 1) return fail(PYJAC_E_INVALID, "reps and n_states must be positive");
-  pyjac_status rc = check_common(m, n, ld, phi, p);
+  // the concentration form takes no pressure array (p may be NULL)
+  pyjac_status rc = check_common(m, n, ld, phi, which == 2 ? phi : p);
   if (rc != PYJAC_OK) return rc;
   if (!out || misaligned(out)) return fail(PYJAC_E_INVALID, "out is NULL or not 8-byte aligned");
   if (n_entries) *n_entries = 0;
@@ -402,14 +478,19 @@ pyjac_status pyjac_mech_autotune(pyjac_mech* m, int32_t which, int64_t n, int64_
   float best_ms = 0.0f;
   int count = 0;
   rc = PYJAC_OK;
-  for (auto& q : shapes_all) {
-    const Variant v{q[0], q[1]};
+  const bool conc = which == 2;
+  const int n_shapes = conc ? (int)(sizeof(kConcShapes) / sizeof(kConcShapes[0]))
+                            : (int)(sizeof(shapes_all) / sizeof(shapes_all[0]));
+  for (int si = 0; si < n_shapes; ++si) {
+    const Variant v = conc ? Variant{kConcShapes[si][0], kConcShapes[si][1]}
+                           : Variant{shapes_all[si][0], shapes_all[si][1]};
     if (kpt_of(m->host.N, v.ts, v.nt) > 8) continue;
-    const size_t lds = tile_lds_bytes(m->host.N, m->host.NR, m->host.NG, v.ts, v.nt, jac);
+    const size_t lds = kind_lds(m, which, v);
     if (lds > m->max_lds) continue;
-    if ((rc = ensure_var(m, v, jac)) != PYJAC_OK) break;
-    const MechDev md = launch_view(m, v, jac);
+    if ((rc = ensure_var(m, v, jac || conc)) != PYJAC_OK) break;
+    const MechDev md = launch_view(m, v, jac || conc);
     auto launch = [&]() {
+      if (conc) return launch_conc(v.ts, v.nt, md, n, ld, phi, out, lds, st);
       return jac ? launch_tile(true, v.ts, v.nt, md, n, ld, phi, p, nullptr, nullptr, nullptr, nullptr,
                                nullptr, out, lds, st)
                  : launch_tile(false, v.ts, v.nt, md, n, ld, phi, p, nullptr, nullptr, nullptr, nullptr,
@@ -447,18 +528,18 @@ pyjac_status pyjac_mech_autotune(pyjac_mech* m, int32_t which, int64_t n, int64_
   hipSetDevice(prev);
   if (rc != PYJAC_OK) return rc;
   if (!best.ts) return fail(PYJAC_E_UNSUPPORTED, "no launch shape fits");
-  (jac ? m->jac_var : m->rates_var) = best;
+  (conc ? m->conc_var : jac ? m->jac_var : m->rates_var) = best;
   if (n_entries) *n_entries = count < max_entries ? count : max_entries;
   return PYJAC_OK;
 }
 
 pyjac_status pyjac_mech_get_variant(const pyjac_mech* m, int32_t which, int32_t* ts, int32_t* nt,
                                     size_t* lds_bytes) {
-  if (!m || (which != 0 && which != 1)) return fail(PYJAC_E_INVALID, "bad handle or kernel id");
-  const Variant v = which ? m->jac_var : m->rates_var;
+  if (!m || which < 0 || which > 2) return fail(PYJAC_E_INVALID, "bad handle or kernel id");
+  const Variant v = which == 2 ? m->conc_var : which ? m->jac_var : m->rates_var;
   if (ts) *ts = v.ts;
   if (nt) *nt = v.nt;
-  if (lds_bytes) *lds_bytes = tile_lds_bytes(m->host.N, m->host.NR, m->host.NG, v.ts, v.nt, which == 1);
+  if (lds_bytes) *lds_bytes = v.ts ? kind_lds(m, which, v) : 0;
   return PYJAC_OK;
 }
 

@@ -40,6 +40,8 @@ constexpr double kInvLn10 = 0.4342944819032518277;
 constexpr int NSC = 16;
 enum { SC_T = 0, SC_IT, SC_LT, SC_P, SC_LP, SC_L10P, SC_RHO, SC_W, SC_M, SC_CP, SC_DCP, SC_SHW, SC_J00, SC_HA, SC_HB,
        SC_IRHO };
+// per-state scalars of the concentration-based form, in the same rows
+enum { SC_IM = SC_RHO, SC_DEN = SC_CP, SC_SUW = SC_DCP, SC_SUU = SC_SHW };
 
 // LDS layout in doubles; each entry counts rows of TS doubles.
 struct TileLayout {
@@ -82,19 +84,25 @@ __device__ inline const double* nasa_coeffs(const MechDev& md, int k, double T) 
 
 // Per-reaction evaluation for one state.  Xs points at X[0][s] (stride TS);
 // R is the reaction's packed record, fetched by the caller before any branch.
-template <int TS, bool JAC>
+// CV selects the concentration-based, constant-volume form: temperature
+// derivatives at constant concentrations (P_r moves with T only through
+// k_0/k_inf, a third-body concentration not at all), the pressure
+// p = R T sum [X] enters PLOG and Chebyshev rates, and the dense part of
+// d q_i / d[X_j] (the all-species collider baseline and the pressure
+// dependence) is returned in o.a; iM = 1 / sum [X] is then used.
+template <int TS, bool JAC, bool CV = false>
 __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const RxnRec* __restrict__ Rg,
                                      const double* Xs,
                                      const double* Bks, const double* dBks, double T, double iT,
                                      double lT, double lp, double l10p, double rho, double irho,
-                                     double W, double M, RxnResult& o) {
+                                     double W, double M, RxnResult& o, double iM = 0.0) {
   const int info = R.info;
   const int kind = info & 0xF, blend = (info >> 4) & 0xF, rev = (info >> 8) & 0xF,
             coll = (info >> 12) & 0xF;
   const double* ar = R.arr;          // primary Arrhenius (hot part of the record)
   const double* arg = Rg->arr;       // secondary / reverse parameters, read where needed
   // ---- forward rate coefficient and D_f = T dln k_f/dT (Sec. 2.3, 2.3.4; Sec. 3.1)
-  double kf, Df;
+  double kf, Df, Dp = 0.0;            // Dp = d ln k_f / d ln p (CV form only)
   if (kind <= K_CHEMACT) {
     kf = ar[0] * exp(ar[1] * lT - ar[2] * iT);
     Df = ar[1] + ar[2] * iT;
@@ -103,19 +111,24 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
     const double* pl = md.plog;
     int lo = p0;
     double frac = 0.0;
+    bool inside = false;
     if (p1 - p0 > 1 && lp > pl[4 * p0]) {
       if (lp >= pl[4 * (p1 - 1)]) lo = p1 - 1;
       else {
         for (int q = p0; q < p1 - 1; ++q) if (pl[4 * q] <= lp) lo = q;
         frac = (lp - pl[4 * lo]) / (pl[4 * (lo + 1)] - pl[4 * lo]);
+        inside = true;
       }
     }
     double lk1 = pl[4 * lo + 1] + pl[4 * lo + 2] * lT - pl[4 * lo + 3] * iT;
     double D1 = pl[4 * lo + 2] + pl[4 * lo + 3] * iT;
-    if (frac != 0.0) {
+    // inside the grid ln k is linear in ln p over the bracket; on a grid point
+    // the derivative is the slope of the bracket that starts there
+    if (CV ? inside : frac != 0.0) {
       int hi = lo + 1;
       double lk2 = pl[4 * hi + 1] + pl[4 * hi + 2] * lT - pl[4 * hi + 3] * iT;
       double D2 = pl[4 * hi + 2] + pl[4 * hi + 3] * iT;
+      if (CV) Dp = (lk2 - lk1) / (pl[4 * hi] - pl[4 * lo]);
       lk1 = lk1 + (lk2 - lk1) * frac;
       D1 = D1 + (D2 - D1) * frac;
     }
@@ -127,18 +140,26 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
     const double xT = cb[2] * iT + cb[3];
     const double xP = cb[4] * l10p + cb[5];
     const double* eta = cb + 6;
-    double val = 0.0, dval = 0.0;
+    double val = 0.0, dval = 0.0, pval = 0.0;
     double Tm1 = 0.0, Tc = 1.0;        // T_{a-1}, T_a of the temperature variable
     double Um2 = 0.0, Um1 = 0.0;       // U_{a-2}, U_{a-1}
     for (int a = 0; a < nT; ++a) {
-      double e = 0.0, Pm1 = 0.0, Pc = 1.0;
+      double e = 0.0, ep = 0.0, Pm1 = 0.0, Pc = 1.0;
+      double Qm2 = 0.0, Qm1 = 0.0;     // U_{b-2}, U_{b-1} of the pressure variable
       for (int b = 0; b < nP; ++b) {
         e += eta[a * nP + b] * Pc;
+        if (CV) {
+          if (b > 0) ep += eta[a * nP + b] * b * Qm1;      // dT_b/dx = b U_{b-1}
+          const double Qn = (b == 0) ? 1.0 : ((b == 1) ? 2.0 * xP : 2.0 * xP * Qm1 - Qm2);
+          Qm2 = Qm1;
+          Qm1 = Qn;
+        }
         double Pn = (b == 0) ? xP : 2.0 * xP * Pc - Pm1;
         Pm1 = Pc;
         Pc = Pn;
       }
       val += e * Tc;
+      if (CV) pval += ep * Tc;
       if (a > 0) dval += e * a * Um1;
       double Tn = (a == 0) ? xT : 2.0 * xT * Tc - Tm1;
       Tm1 = Tc;
@@ -149,6 +170,7 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
     }
     kf = exp(kLn10 * val);
     Df = -kLn10 * dval * cb[2] * iT;
+    if (CV) Dp = pval * cb[4];         // d log10 k / d log10 p
   }
   // ---- reverse rate coefficient (Sec. 2.3.1)
   double kr = 0.0, Dr = 0.0;
@@ -163,7 +185,7 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
       if (JAC) sdB += nu * dBks[k * TS];
     }
     kr = kf * exp(-sB - R.dnu_lnpr);
-    Dr = Df - T * sdB;
+    Dr = Df - T * sdB;                 // K_c depends on T only: d ln k_r / d ln p = Dp
   } else if (rev == R_EXPLICIT) {
     kr = arg[6] * exp(arg[7] * lT - arg[8] * iT);
     Dr = arg[7] + arg[8] * iT;
@@ -197,7 +219,7 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
     if (kind == K_THD) {
       c = E;
       psi = 1.0;
-      dcdT = -E * iT;
+      dcdT = CV ? 0.0 : -E * iT;       // constant p: [X] ~ 1/T; constant volume: fixed
     } else {
       const double ratio = arg[3] * exp(arg[4] * lT - arg[5] * iT);   // k0 / kinf
       const double Pr = ratio * E;
@@ -246,7 +268,8 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
         Lam = -lnb * Xs_ * Xs_ * 2.0 * lPr * kInvLn10;
         dlnFdT = fp[4] * iT + Xs_ * dbase / base;
       }
-      const double dlnPr = (arg[4] + arg[5] * iT - 1.0) * iT;   // (1/Pr) dPr/dT
+      // (1/Pr) dPr/dT: through k_0/k_inf, and at constant p through [X]_i ~ 1/T
+      const double dlnPr = (arg[4] + arg[5] * iT - (CV ? 0.0 : 1.0)) * iT;
       double Phi;
       const double i1p = 1.0 / (1.0 + Pr);
       if (kind == K_FALLOFF) {
@@ -267,7 +290,19 @@ __device__ inline void eval_reaction(const MechDev& md, const RxnRec& R, const R
   o.Rr = Rr;
   o.c = c;
   o.q = c * Rn;
-  if (JAC) {
+  if (JAC && CV) {
+    // d ln k / dT at constant concentrations: (D + Dp) / T, since d ln p / dT = 1/T
+    const double Dpr = rev == R_KC ? Dp : 0.0;
+    o.thT = dcdT * Rn + c * (Rf * (Df + Dp) - Rr * (Dr + Dpr)) * iT;
+    const double Gv = psi * Rn;
+    // dense part of dq/d[X_j]: the collider baseline alpha = 1 of an
+    // all-species third body, and the pressure through d ln p / d[X_j] = 1/sum[X]
+    o.a = ((coll == C_EFF || coll == C_UNITY) ? Gv : 0.0) + c * (Rf * Dp - Rr * Dpr) * iM;
+    o.b = 0.0;
+    o.KF = c * kf;
+    o.KR = c * kr;
+    o.G = Gv;
+  } else if (JAC) {
     const int sf = R.sum_f, sr = R.sum_r;
     const double dRdT = (Rf * (Df - sf) - Rr * (Dr - sr)) * iT;
     o.thT = (dcdT * Rn + c * (dRdT + Rn * iT)) * irho;
@@ -713,6 +748,258 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
   }
 }
 
+// ---------------------------------------------- concentration-based Jacobian
+// State {T, [X_1..X_N]} of a constant-volume reactor (Sec. 3.3's sparse
+// formulation): d[X_k]/dt = wdot_k, dT/dt = -sum U_k wdot_k / sum [X_k] C_v,k
+// with U_k = H_k - R T, C_v,k = C_p,k - R (molar).  Output per state, element
+// e at out[e*ld + s]:
+//   e = 0            J_00 = d(dT/dt)/dT
+//   e = 1 .. N       J_k0 = d wdot_k / dT
+//   e = N+1 .. 2N    J_0j = d(dT/dt)/d[X_j]
+//   e = 2N+1 .. 3N   u_k, the dense part of row k: J_kj = u_k + S_kj
+//   e = 3N+1 + q     value q of the sparse part S in compressed-column order
+// The tile mapping and the reaction phase are those of tile_kernel; phase D
+// streams only the rows with terms and stores each once.
+struct CvLayout {
+  int X, KF, KR, G, SC, alias, Bk, dBk, chunk, H, red, rows;
+  __host__ __device__ CvLayout(int N, int NR, int NG, int Gr) {
+    X = 0;
+    KF = X + N + 1;
+    KR = KF + NR;
+    G = KR + NR;
+    SC = G + NG;
+    alias = SC + NSC;
+    Bk = alias;                         // phases A, B
+    dBk = Bk + N;
+    chunk = dBk + N;
+    H = alias;                          // phases C, D: U_k (row N: slack)
+    red = H + N + 1;                    // five per-species sum terms [5][N]
+    const int endB = chunk + 4 * Gr, endC = red + 5 * N;
+    rows = endB > endC ? endB : endC;
+  }
+};
+
+template <int TS, int NT, int KPT>
+__global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void conc_tile_kernel(MechDev md, int64_t n, int64_t ld,
+                                                                           const double* __restrict__ phi,
+                                                                           double* __restrict__ out) {
+  constexpr int Gr = NT / TS;
+  extern __shared__ double lds[];
+  const int N = md.N, NR = md.NR, NG = md.NG;
+  const int tid = threadIdx.x, s = tid % TS, g = tid / TS;
+  const int64_t sg = (int64_t)xcd_tile() * TS + s;
+  const bool live = sg < n;
+  const int64_t sl = live ? sg : n - 1;
+  const CvLayout L(N, NR, NG, Gr);
+  double* X = lds + (size_t)L.X * TS + s;
+  double* SC = lds + (size_t)L.SC * TS + s;
+  double* Bk = lds + (size_t)L.Bk * TS + s;
+  double* dBk = lds + (size_t)L.dBk * TS + s;
+
+  // ---- phase A: concentrations are the state; p = R T sum [X] (Eq. state)
+  for (int k = g; k < N; k += Gr) X[k * TS] = phi[(int64_t)(k + 1) * ld + sl];
+  __syncthreads();
+  if (g == 0) {
+    double c4[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k + 4 <= N; k += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) c4[u] += X[(k + u) * TS];
+    }
+    for (int u = 0; k < N; ++k, ++u) c4[u] += X[k * TS];
+    const double M = (c4[0] + c4[1]) + (c4[2] + c4[3]);
+    const double T = phi[sl];
+    const double p = kR * T * M;
+    X[N * TS] = 1.0;
+    SC[SC_T * TS] = T;
+    SC[SC_IT * TS] = 1.0 / T;
+    SC[SC_LT * TS] = log(T);
+    SC[SC_P * TS] = p;
+    const double lp = log(p);
+    SC[SC_LP * TS] = lp;
+    SC[SC_L10P * TS] = lp * kInvLn10;
+    SC[SC_M * TS] = M;
+    SC[SC_IM * TS] = 1.0 / M;
+  }
+  __syncthreads();
+  for (int k = g; k < N; k += Gr) {
+    const double T = SC[SC_T * TS], iT = SC[SC_IT * TS], lT = SC[SC_LT * TS];
+    const double* a = nasa_coeffs(md, k, T);
+    Bk[k * TS] = a[6] - a[0] + (a[0] - 1.0) * lT +
+                 T * (a[1] * 0.5 + T * (a[2] * (1.0 / 6.0) + T * (a[3] * (1.0 / 12.0) + a[4] * 0.05 * T))) -
+                 a[5] * iT;
+    dBk[k * TS] = (a[0] - 1.0 + a[5] * iT) * iT + a[1] * 0.5 +
+                  T * (a[2] * (1.0 / 3.0) + T * (a[3] * 0.25 + a[4] * 0.2 * T));
+  }
+  __syncthreads();
+
+  // ---- phase B: reactions in chunks, gathered per species (no atomics):
+  // acc 0 wdot_k, 1 d wdot_k/dT, 2 u_k
+  double* chunk = lds + (size_t)L.chunk * TS + s;
+  double* KF = lds + (size_t)L.KF * TS + s;
+  double* KR = lds + (size_t)L.KR * TS + s;
+  double* Gs = lds + (size_t)L.G * TS + s;
+  double acc[KPT][3];
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
+  for (int c0 = 0, ch = 0; c0 < NR; c0 += Gr, ++ch) {
+    const int i = c0 + g;
+    const int* bnd = md.spg_chunk + (size_t)ch * N;
+    int gb0[KPT], gb1[KPT];
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int k = min(g + q * Gr, N - 1);
+      gb0[q] = bnd[k];
+      gb1[q] = bnd[N + k];
+    }
+    if (i < NR) {
+      RxnRec Rr;
+      {
+        const int4* src = reinterpret_cast<const int4*>(md.rx + i);
+        int4* dst = reinterpret_cast<int4*>(&Rr);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) dst[u] = src[u];
+      }
+      RxnResult o;
+      eval_reaction<TS, true, true>(md, Rr, md.rx + i, X, Bk, dBk, SC[SC_T * TS], SC[SC_IT * TS],
+                                    SC[SC_LT * TS], SC[SC_LP * TS], SC[SC_L10P * TS], 0.0, 0.0, 0.0,
+                                    SC[SC_M * TS], o, SC[SC_IM * TS]);
+      chunk[g * TS] = o.q;
+      chunk[(Gr + g) * TS] = o.thT;
+      chunk[(2 * Gr + g) * TS] = o.a;
+      KF[i * TS] = o.KF;
+      KR[i * TS] = o.KR;
+      if (Rr.gslot >= 0) Gs[Rr.gslot * TS] = o.G;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int k = g + q * Gr;
+      if (k < N) {
+        const int e1 = gb1[q];
+        for (int e = gb0[q]; e < e1; e += 4) {
+          int ent[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) ent[u] = md.spg_ent[e + u];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (e + u < e1) {
+              const int r = (ent[u] & 0xFFFF) - c0;
+              const double nu = (double)(ent[u] >> 16);
+              acc[q][0] += nu * chunk[r * TS];
+              acc[q][1] += nu * chunk[(Gr + r) * TS];
+              acc[q][2] += nu * chunk[(2 * Gr + r) * TS];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- phase C: temperature column, dense row parts, temperature-row sums
+  double* H = lds + (size_t)L.H * TS + s;
+  double* red = lds + (size_t)L.red * TS + s;
+  {
+    const double T = SC[SC_T * TS];
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int k = g + q * Gr;
+      if (k < N) {
+        const double* a = nasa_coeffs(md, k, T);
+        const double cpR = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + a[4] * T)));
+        const double hRT = a[0] + T * (a[1] * 0.5 + T * (a[2] * (1.0 / 3.0) + T * (a[3] * 0.25 + a[4] * 0.2 * T))) +
+                           a[5] / T;
+        const double U = kR * T * (hRT - 1.0);                  // molar internal energy
+        const double Cv = kR * (cpR - 1.0);                      // molar C_v
+        const double dCv = kR * (a[1] + T * (2.0 * a[2] + T * (3.0 * a[3] + 4.0 * a[4] * T)));
+        const double Ck = X[k * TS];
+        H[k * TS] = U;
+        red[k * TS] = U * acc[q][0];
+        red[(N + k) * TS] = Ck * Cv;
+        red[(2 * N + k) * TS] = Cv * acc[q][0] + U * acc[q][1];
+        red[(3 * N + k) * TS] = Ck * dCv;
+        red[(4 * N + k) * TS] = U * acc[q][2];
+        if (live) {
+          out[(int64_t)(1 + k) * ld + sg] = acc[q][1];
+          out[(int64_t)(2 * N + 1 + k) * ld + sg] = acc[q][2];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (g < 5) {
+    // five per-state sums over species, each by one thread group in a fixed
+    // order (four interleaved partial sums)
+    double p4[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* r = red + (size_t)g * N * TS;
+    int k = 0;
+    for (; k + 4 <= N; k += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) p4[u] += r[(k + u) * TS];
+    }
+    for (int u = 0; k < N; ++k, ++u) p4[u] += r[k * TS];
+    const double v = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+    // sums: 0 sum U wdot, 1 D = sum [X] C_v, 2 sum (C_v wdot + U dwdot/dT),
+    // 3 sum [X] dC_v/dT, 4 sum U u
+    SC[(g == 0 ? SC_SUW : g == 1 ? SC_DEN : g == 4 ? SC_SUU : (g == 2 ? SC_J00 : SC_HA)) * TS] = v;
+  }
+  __syncthreads();
+  const double D = SC[SC_DEN * TS], SUw = SC[SC_SUW * TS], SUu = SC[SC_SUU * TS];
+  const double iD = 1.0 / D;
+  if (g == 0 && live) out[sg] = (-SC[SC_J00 * TS] + SUw * SC[SC_HA * TS] * iD) * iD;
+
+  // ---- phase D: sparse part, one column stream per group (present rows)
+  const double T = SC[SC_T * TS];
+  const double* Xb = lds + (size_t)L.X * TS + s;
+  for (int jc = g; jc < N; jc += Gr) {
+    const int j = md.cv_col_order[jc];
+    const ColRec* rec = md.cv_colrec + md.cv_col_start[j];
+    const int cnt = md.cv_col_start[j + 1] - md.cv_col_start[j];
+    // lanes past the batch end store the last state's (identical) values
+    double* outp = out + (int64_t)(3 * N + 1 + md.cv_colptr[j]) * ld + sl;
+    double val = 0.0, hk = 0.0, TR = 0.0;
+    int k = N;                          // no row open before the first marker
+    auto batch = [&](const ColRec (&r)[kColBatch]) {
+      double t[kColBatch];
+#pragma unroll
+      for (int u = 0; u < kColBatch; ++u) {
+        const int x = r[u].x;
+        t[u] = r[u].coef * Xb[r[u].src * TS] * Xb[(x & 0x7FFF) * TS] * Xb[((x >> 15) & 0x7FFF) * TS];
+      }
+#pragma unroll
+      for (int u = 0; u < kColBatch; ++u) {
+        val += t[u];
+        if (r[u].x & kColMark) {       // ends the open row (if any), opens row src
+          if (k < N) {
+            *outp = val;
+            outp += ld;
+            TR += hk * val;
+          }
+          k = r[u].src;
+          val = 0.0;
+          hk = H[k * TS];              // row N: slack, never used
+        }
+      }
+    };
+    ColRec ra[kColBatch], rb[kColBatch];
+#pragma unroll
+    for (int u = 0; u < kColBatch; ++u) ra[u] = rec[u];
+    for (int b = 0; b < cnt; b += 2 * kColBatch) {
+#pragma unroll
+      for (int u = 0; u < kColBatch; ++u) rb[u] = rec[b + kColBatch + u];
+      batch(ra);
+#pragma unroll
+      for (int u = 0; u < kColBatch; ++u) ra[u] = rec[b + 2 * kColBatch + u];
+      batch(rb);
+    }
+    // temperature row: sum_k U_k J_kj = sum_k U_k S_kj + sum_k U_k u_k
+    const double* aj = nasa_coeffs(md, j, T);
+    const double Cvj = kR * (aj[0] + T * (aj[1] + T * (aj[2] + T * (aj[3] + aj[4] * T))) - 1.0);
+    if (live) out[(int64_t)(N + 1 + j) * ld + sg] = (-(TR + SUu) + SUw * Cvj * iD) * iD;
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 size_t tile_lds_bytes(int N, int NR, int NG, int TS, int NT, bool jac) {
   TileLayout L(N, NR, NG, NT / TS, jac);
@@ -739,6 +1026,44 @@ static hipError_t launch_k(int kpt, const MechDev& md, int64_t n, int64_t ld, co
   if (kpt <= 2) return launch_t<TS, NT, 2, JAC, SPLIT>(md, n, ld, phi, p, a, b, c, d, e, jac, lds, st);
   if (kpt <= 4) return launch_t<TS, NT, 4, JAC, SPLIT>(md, n, ld, phi, p, a, b, c, d, e, jac, lds, st);
   if (kpt <= 8) return launch_t<TS, NT, 8, JAC, SPLIT>(md, n, ld, phi, p, a, b, c, d, e, jac, lds, st);
+  return hipErrorInvalidValue;
+}
+
+size_t conc_lds_bytes(int N, int NR, int NG, int TS, int NT) {
+  CvLayout L(N, NR, NG, NT / TS);
+  return (size_t)L.rows * TS * sizeof(double);
+}
+
+template <int TS, int NT, int KPT>
+static hipError_t launch_conc_t(const MechDev& md, int64_t n, int64_t ld, const double* phi, double* out,
+                                size_t lds, hipStream_t st) {
+  auto kern = conc_tile_kernel<TS, NT, KPT>;
+  hipError_t err = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  const int64_t tiles = (n + TS - 1) / TS;
+  hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(NT), lds, st, md, n, ld, phi, out);
+  return hipGetLastError();
+}
+
+// Concentration-form Jacobian launch; shapes (TS, NT) as listed in the body.
+hipError_t launch_conc(int TS, int NT, const MechDev& md, int64_t n, int64_t ld, const double* phi, double* out,
+                       size_t lds, hipStream_t st) {
+  const int kpt = (md.N + NT / TS - 1) / (NT / TS);
+#define PYJAC_CONC(ts, nt)                                                             \
+  if (TS == ts && NT == nt) {                                                          \
+    if (kpt <= 1) return launch_conc_t<ts, nt, 1>(md, n, ld, phi, out, lds, st);       \
+    if (kpt <= 2) return launch_conc_t<ts, nt, 2>(md, n, ld, phi, out, lds, st);       \
+    if (kpt <= 4) return launch_conc_t<ts, nt, 4>(md, n, ld, phi, out, lds, st);       \
+    if (kpt <= 8) return launch_conc_t<ts, nt, 8>(md, n, ld, phi, out, lds, st);       \
+    return hipErrorInvalidValue;                                                       \
+  }
+  PYJAC_CONC(16, 1024)
+  PYJAC_CONC(8, 512)
+  PYJAC_CONC(8, 1024)
+  PYJAC_CONC(4, 512)
+  PYJAC_CONC(4, 1024)
+  PYJAC_CONC(2, 512)
+#undef PYJAC_CONC
   return hipErrorInvalidValue;
 }
 

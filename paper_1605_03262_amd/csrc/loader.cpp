@@ -528,6 +528,62 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
       // one batch of slack: the kernel reads one batch past a column's stream
       for (int u = 0; u < kColBatch; ++u) P.colrec.push_back(ColRec{0.0, N, N | (N << 15)});
     }
+    // ---- concentration-based, constant-volume form (state {T, [X_1..X_N]}):
+    // d wdot_k / d[X_l] = sum_i nu_ki dq_i/d[X_l]; the mass-action and
+    // non-unit-collider parts are the sparse terms (every species l is a state
+    // variable, no molecular-weight ratios); the all-species collider baseline
+    // and the pressure dependence form the dense vector u computed per state.
+    {
+      std::vector<Term> tv;
+      for (int slot = 0; slot < NR; ++slot) {
+        const RawRxn& r = m.rxn[order[slot]];
+        std::map<int, int> netnu;
+        for (auto& q : r.reac) netnu[q.first] -= q.second;
+        for (auto& q : r.prod) netnu[q.first] += q.second;
+        for (auto& [k, nu_k] : netnu) {
+          if (!nu_k) continue;
+          for (auto& q : r.reac) tv.push_back({q.first, k, slot, cofactors(r.reac, q.first), (double)nu_k * q.second});
+          if (r.rev != R_IRREV)
+            for (auto& q : r.prod)
+              tv.push_back({q.first, k, NR + slot, cofactors(r.prod, q.first), -(double)nu_k * q.second});
+          const int g = P.rx[slot].gslot;
+          if (r.coll == C_EFF) {
+            for (auto& [l, a] : r.eff)
+              if (a != 1.0) tv.push_back({l, k, 2 * NR + g, N | (N << 15), nu_k * (a - 1.0)});
+          } else if (r.coll == C_SPECIES) {
+            tv.push_back({r.m, k, 2 * NR + g, N | (N << 15), (double)nu_k});
+          }
+        }
+      }
+      std::stable_sort(tv.begin(), tv.end(), [](const Term& a, const Term& b) {
+        return a.j != b.j ? a.j < b.j : a.k < b.k;
+      });
+      size_t t = 0;
+      P.cv_colptr.push_back(0);
+      for (int j = 0; j < N; ++j) {
+        P.cv_col_start.push_back((int)P.cv_colrec.size());
+        std::vector<int> rows;
+        for (size_t u = t; u < tv.size() && tv[u].j == j; ++u)
+          if (rows.empty() || rows.back() != tv[u].k) rows.push_back(tv[u].k);
+        for (int k : rows) P.cv_rowidx.push_back(k);
+        P.cv_colptr.push_back((int)P.cv_rowidx.size());
+        P.cv_colrec.push_back(ColRec{0.0, rows.empty() ? N : rows[0], N | (N << 15) | kColMark});
+        for (size_t q = 0; q < rows.size(); ++q) {
+          for (; t < tv.size() && tv[t].j == j && tv[t].k == rows[q]; ++t)
+            P.cv_colrec.push_back(ColRec{tv[t].coef, N + 1 + tv[t].src, tv[t].x});
+          const int next = q + 1 < rows.size() ? rows[q + 1] : N;
+          P.cv_colrec.push_back(ColRec{0.0, next, N | (N << 15) | kColMark});
+        }
+        while (P.cv_colrec.size() % (2 * kColBatch)) P.cv_colrec.push_back(ColRec{0.0, N, N | (N << 15)});
+      }
+      P.cv_col_start.push_back((int)P.cv_colrec.size());
+      for (int u = 0; u < kColBatch; ++u) P.cv_colrec.push_back(ColRec{0.0, N, N | (N << 15)});
+      P.cv_col_order.resize(N);
+      std::iota(P.cv_col_order.begin(), P.cv_col_order.end(), 0);
+      std::stable_sort(P.cv_col_order.begin(), P.cv_col_order.end(), [&](int a, int b) {
+        return P.cv_col_start[a + 1] - P.cv_col_start[a] > P.cv_col_start[b + 1] - P.cv_col_start[b];
+      });
+    }
     // The groups of a wavefront stream their columns in lockstep, so columns
     // go out longest first: neighbouring groups get streams of similar length.
     P.col_order.resize(N - 1);

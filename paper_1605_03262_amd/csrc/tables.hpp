@@ -93,6 +93,15 @@ struct PackedMech {
   std::vector<int> col_order;                             // [N-1] columns, longest stream first
   std::vector<uint32_t> col_flags;                        // [N-1][colFlagWords(N)] present rows
   int col_split = 0;                                      // column-stream form (see ColRec)
+  // Concentration-based, constant-volume Jacobian: species block
+  // J[k][j] = u_k + S[k][j] with S sparse.  Per species column j (all N):
+  // a present-rows stream (as col_split = 1, without the dense pass; coef
+  // without molecular-weight ratios, every species a state variable) and
+  // the compressed-column pattern of S (rows with terms, ascending).
+  std::vector<int> cv_col_start;                          // [N + 1]
+  std::vector<ColRec> cv_colrec;
+  std::vector<int> cv_col_order;                          // [N] longest stream first
+  std::vector<int> cv_colptr, cv_rowidx;                  // [N + 1], [nnz]
 };
 
 constexpr int colFlagWords(int N) { return (N + 31) / 32; }
@@ -125,6 +134,10 @@ struct MechDev {
   const ColRec* __restrict__ colrec;
   const int* __restrict__ col_order;    // [N-1] longest column stream first
   const uint32_t* __restrict__ col_flags;  // [N-1][colFlagWords(N)]
+  const int* __restrict__ cv_col_start;    // [N + 1]
+  const ColRec* __restrict__ cv_colrec;
+  const int* __restrict__ cv_col_order;    // [N]
+  const int* __restrict__ cv_colptr;       // [N + 1]
 };
 
 }  // namespace pyjac
