@@ -203,6 +203,20 @@ pyjac_status pyjac_sdirk3_step(const pyjac_mech* mech, int64_t n_states, int64_t
                                double* phi_out, double* dnorm, void* workspace, size_t workspace_bytes,
                                void* stream);
 
+/* Mixing fractional step of a partially stirred reactor (App. C): for every
+ * particle s with partner q = partner[s] (0 <= q < n_states; a negative value
+ * leaves s unchanged), the mixture enthalpy h and the mass fractions relax
+ * towards the partner's, x_s <- x_s - weight (x_s - x_q) with weight =
+ * (1 - exp(-2 dt_sub / tau_mix)) / 2 in [0, 1/2], and the temperature is
+ * recovered from the mixed enthalpy (Newton on h(T) = sum_k Y_k h_k(T),
+ * Sec. 2.2).  phi, phi_out [N][ld] as pyjac_eval_rates' phi (phi_out must not
+ * alias phi: both members of a pair read the old states); partner [ld] int32
+ * device array.  Pairs are symmetric in the PaSR driver, so the pair's
+ * enthalpy and mass are conserved.  Errors: PYJAC_E_INVALID,
+ * PYJAC_E_UNSUPPORTED (more than 1024 species), PYJAC_E_DEVICE. */
+pyjac_status pyjac_mix_pairs(const pyjac_mech* mech, int64_t n_states, int64_t ld, const double* phi,
+                             const int32_t* partner, double weight, double* phi_out, void* stream);
+
 /* Bytes of device workspace pyjac_newton_factor_solve needs for n_states
  * states in `mode` (0 or 1; with PYJAC_NEWTON_KEEP_FACTOR including the kept
  * factor's storage; PYJAC_NEWTON_REUSE_FACTOR is ignored here).

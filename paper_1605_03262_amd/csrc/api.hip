@@ -19,6 +19,8 @@ namespace pyjac {
 
 size_t tile_lds_bytes(int N, int NR, int NG, int TS, int NT, bool jac);
 size_t conc_lds_bytes(int N, int NR, int NG, int TS, int NT);
+hipError_t launch_mix_pairs(const MechDev& md, int64_t n, int64_t ld, const double* phi, const int* partner, double w,
+                            double* out, hipStream_t st);
 hipError_t launch_conc(int TS, int NT, const MechDev& md, int64_t n, int64_t ld, const double* phi, double* out,
                        size_t lds, hipStream_t st);
 hipError_t launch_tile(bool jac_mode, int TS, int NT, const MechDev& md, int64_t n, int64_t ld,
@@ -367,6 +369,25 @@ pyjac_status pyjac_eval_jacobian_conc(const pyjac_mech* m, int64_t n, int64_t ld
   const MechDev md = launch_view(m, v, true);
   hipError_t e = launch_conc(v.ts, v.nt, md, n, ld, phi_c, jac, lds, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("jacobian launch failed: ") + hipGetErrorString(e));
+  return PYJAC_OK;
+}
+
+pyjac_status pyjac_mix_pairs(const pyjac_mech* m, int64_t n, int64_t ld, const double* phi, const int32_t* partner,
+                             double weight, double* phi_out, void* stream) {
+  if (!m) return fail(PYJAC_E_INVALID, "mechanism handle is NULL");
+  if (n < 0 || ld < n) return fail(PYJAC_E_INVALID, "bad n_states / ld");
+  if (!(weight >= 0.0 && weight <= 0.5)) return fail(PYJAC_E_INVALID, "weight must lie in [0, 1/2]");
+  if (n == 0) return PYJAC_OK;
+  if (!phi || !partner || !phi_out) return fail(PYJAC_E_INVALID, "NULL array argument");
+  if (phi_out == phi) return fail(PYJAC_E_INVALID, "phi_out may not alias phi");
+  if (misaligned(phi) || misaligned(phi_out) || (reinterpret_cast<uintptr_t>(partner) & 3u))
+    return fail(PYJAC_E_INVALID, "pointer not aligned");
+  if (m->host.N > 1024) return fail(PYJAC_E_UNSUPPORTED, "more than 1024 species");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != m->device)
+    return fail(PYJAC_E_INVALID, "current HIP device differs from the mechanism's device");
+  hipError_t e = launch_mix_pairs(m->dev, n, ld, phi, partner, weight, phi_out, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("mixing launch failed: ") + hipGetErrorString(e));
   return PYJAC_OK;
 }
 

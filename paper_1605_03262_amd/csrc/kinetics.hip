@@ -27,6 +27,7 @@
 // and is accumulated while the species rows of a column are stored.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -998,6 +999,77 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void conc_tile_kernel(Mech
     const double Cvj = kR * (aj[0] + T * (aj[1] + T * (aj[2] + T * (aj[3] + aj[4] * T))) - 1.0);
     if (live) out[(int64_t)(N + 1 + j) * ld + sg] = (-(TR + SUu) + SUw * Cvj * iD) * iD;
   }
+}
+
+// ------------------------------------------------- PaSR mixing fractional step
+// Pairwise mixing of a partially stirred reactor's particles (App. C): each
+// particle s with a partner q relaxes towards it in mixture enthalpy and mass
+// fractions, phi_s <- phi_s - w (phi_s - phi_q) with w = (1 - exp(-2 dt/tau))/2,
+// and its temperature is recovered from the mixed enthalpy by Newton's method
+// on h(T) = sum_k Y_k h_k(T) (Sec. 2.2 polynomials).  Out of place: every
+// particle reads the old state of both members of its pair.
+__device__ inline double mix_enthalpy(const MechDev& md, double T, const double* Y, double* cp) {
+  double h = 0.0, c = 0.0;
+  for (int k = 0; k < md.N; ++k) {
+    const double* a = nasa_coeffs(md, k, T);
+    const double cpR = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + a[4] * T)));
+    const double hR = T * (a[0] + T * (a[1] * 0.5 + T * (a[2] * (1.0 / 3.0) + T * (a[3] * 0.25 + a[4] * 0.2 * T)))) +
+                      a[5];
+    h += Y[k] * hR * kR * md.invW[k];
+    c += Y[k] * cpR * kR * md.invW[k];
+  }
+  *cp = c;
+  return h;
+}
+
+template <int NMAX>
+__global__ void mix_pairs_kernel(MechDev md, int64_t n, int64_t ld, const double* __restrict__ phi,
+                                 const int* __restrict__ partner, double w, double* __restrict__ out) {
+  const int N = md.N;
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
+    const int q = partner[s];
+    if (q < 0 || q >= n) {
+      for (int e = 0; e < N; ++e) out[(int64_t)e * ld + s] = phi[(int64_t)e * ld + s];
+      continue;
+    }
+    double Ys[NMAX], Yq[NMAX], Ym[NMAX];
+    double ss = 0.0, sq = 0.0;
+    for (int k = 0; k < N - 1; ++k) {
+      Ys[k] = phi[(int64_t)(k + 1) * ld + s];
+      Yq[k] = phi[(int64_t)(k + 1) * ld + q];
+      ss += Ys[k];
+      sq += Yq[k];
+    }
+    Ys[N - 1] = 1.0 - ss;
+    Yq[N - 1] = 1.0 - sq;
+    const double Ts = phi[s], Tq = phi[q];
+    double cp;
+    const double hs = mix_enthalpy(md, Ts, Ys, &cp), hq = mix_enthalpy(md, Tq, Yq, &cp);
+    for (int k = 0; k < N; ++k) Ym[k] = Ys[k] - w * (Ys[k] - Yq[k]);
+    const double hm = hs - w * (hs - hq);
+    double T = Ts - w * (Ts - Tq);
+    for (int it = 0; it < 50; ++it) {
+      const double h = mix_enthalpy(md, T, Ym, &cp);
+      const double dT = (hm - h) / cp;
+      T += dT;
+      if (fabs(dT) <= 1e-13 * T) break;
+    }
+    out[s] = T;
+    for (int k = 0; k < N - 1; ++k) out[(int64_t)(k + 1) * ld + s] = Ym[k];
+  }
+}
+
+hipError_t launch_mix_pairs(const MechDev& md, int64_t n, int64_t ld, const double* phi, const int* partner, double w,
+                            double* out, hipStream_t st) {
+  const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+#define PYJAC_MIX(nm) \
+  if (md.N <= nm) { hipLaunchKernelGGL(mix_pairs_kernel<nm>, dim3(grid), dim3(256), 0, st, md, n, ld, phi, partner, w, out); return hipGetLastError(); }
+  PYJAC_MIX(64)
+  PYJAC_MIX(128)
+  PYJAC_MIX(384)
+  PYJAC_MIX(1024)
+#undef PYJAC_MIX
+  return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------------ launchers

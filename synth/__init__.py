@@ -4,4 +4,4 @@ kinetics arithmetic."""
 from .mechgen import (CONFIGS, Mechanism, Reaction, Species, config_mechanism,  # noqa: F401
                       make_mechanism, tiny_mechanism, ATM)
 from .states import (NEWTON_GAMMA, conditioned_steps, config_states,  # noqa: F401
-                     draw_newton_inputs, draw_states)
+                     draw_newton_inputs, draw_states, pasr_fresh)

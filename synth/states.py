@@ -54,3 +54,19 @@ def conditioned_steps(seed: int, jac_rows: np.ndarray, c_range=(1.0, 3.0e3),
     n = jac_rows.shape[1]
     c = np.exp(rng.uniform(np.log(c_range[0]), np.log(c_range[1]), size=n))
     return c / (gamma * np.max(jac_rows, axis=0))
+
+
+def pasr_fresh(mech, T_in: float, seed: int, inert_fraction: float = 0.72) -> np.ndarray:
+    """Fresh inflow composition of a premixed PaSR (App. C) for a synthetic
+    mechanism, shaped like a fuel/air mixture: the inert last species carries
+    `inert_fraction` of the mass (the N2 of air), three seeded species share
+    the rest, every other species holds a trace of 1e-9.  Returns
+    [T_in, Y_1..Y_{N-1}]."""
+    rng = np.random.default_rng(seed)
+    N = mech.n_species
+    Y = np.full(N, 1e-9)
+    major = rng.choice(N - 1, 3, replace=False)
+    Y[major] = rng.dirichlet(np.full(3, 2.0)) * (1.0 - inert_fraction)
+    Y[N - 1] = 0.0
+    Y[N - 1] = 1.0 - Y.sum()
+    return np.concatenate([[T_in], Y[:-1]])

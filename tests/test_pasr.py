@@ -1,0 +1,93 @@
+"""PaSR particle driver (App. C) on the GPU: the mixing kernel against the
+oracle's mixing step, a short PaSR run producing physical particle states, and
+the Jacobians (mass-fraction and concentration forms) on those states against
+the oracle -- PaSR states are the paper's own test distribution (Sec. 5), with
+fresh, burning, mixed and near-equilibrium compositions."""
+import numpy as np
+import pytest
+
+from synth import ATM, config_mechanism, config_states, pasr_fresh
+from test_gpu_conc import densify
+from test_gpu_parity import check_jac, check_rates, gpu_jac, gpu_rates
+from test_oracle_conc_pins import conc_states
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def Ref(oracle_built):
+    from oracle import RefMech
+    return RefMech
+
+
+@pytest.mark.parametrize("cfg", [0, 1])
+def test_mixing_kernel_matches_oracle(torch, Ref, cfg):
+    from oracle.pasr_ref import mix_pairs
+    from paper_1605_03262_amd import Mechanism, _lib
+    mech = config_mechanism(cfg)
+    phi, _ = config_states(cfg, 64)
+    phi[0, :32] = np.linspace(350.0, 2400.0, 32)
+    rng = np.random.default_rng(cfg)
+    idx = rng.permutation(60)
+    partner = np.full(64, -1, dtype=np.int32)
+    partner[idx[0::2]] = idx[1::2]
+    partner[idx[1::2]] = idx[0::2]
+    w = 0.5 * (1 - np.exp(-2 * 0.04))
+    M = Mechanism(text=mech.to_text())
+    d_phi = torch.from_numpy(phi).cuda()
+    d_out = torch.empty_like(d_phi)
+    d_par = torch.from_numpy(partner).cuda()
+    _lib.pyjac_mix_pairs(M.handle, 64, 64, d_phi.data_ptr(), d_par.data_ptr(), w, d_out.data_ptr(), None)
+    torch.cuda.synchronize()
+    out = d_out.cpu().numpy()
+    ref = mix_pairs(Ref(text=mech.to_text()), mech.molecular_weights(), phi, partner, w)
+    np.testing.assert_allclose(out[0], ref[0], rtol=1e-12)
+    np.testing.assert_allclose(out[1:], ref[1:], rtol=1e-13, atol=1e-16)
+    assert np.array_equal(out[:, 60:], phi[:, 60:])
+
+
+@pytest.mark.parametrize("cfg,n_res,tau_res", [(0, 1.0, 10e-3), (1, 0.5, 5e-3)])
+def test_pasr_states_and_jacobian_parity(torch, Ref, cfg, n_res, tau_res):
+    from paper_1605_03262_amd import Mechanism
+    from paper_1605_03262_amd.pasr import PaSR, burn
+    mech = config_mechanism(cfg)
+    N = mech.n_species
+    M = Mechanism(text=mech.to_text())
+    p_pa = 10 * ATM
+    fresh = pasr_fresh(mech, 600.0, 11 + cfg)
+    hot = fresh.copy()
+    hot[0] = 2000.0
+    pilot = burn(M, hot, p_pa)
+    assert np.all(np.isfinite(pilot))
+    reactor = PaSR(M, n_reactors=4, fresh=fresh, pilot=pilot, p_pa=p_pa, tau_res=tau_res, seed=5 + cfg)
+    phi, p = reactor.run(n_res)
+    assert np.all(np.isfinite(phi))
+    assert np.all(phi[0] > 200.0) and np.all(phi[0] < 5000.0)
+    # the driver keeps steps whose mass fractions lie within 1e-6 of [0, 1]
+    # (implicit steps leave rounding-level negatives; they stay in the set,
+    # since they are states such integrators hand to the Jacobian)
+    assert np.all(phi[1:] > -1e-6) and np.all(phi[1:].sum(axis=0) < 1 + 1e-6)
+    print(f"C{cfg} PaSR: min Y {phi[1:].min():.2e}, frozen particle-steps {getattr(reactor, 'frozen', 0)}")
+    assert np.ptp(phi[0]) > 10.0                         # a spread of particle states
+    ref = Ref(text=mech.to_text())
+    check_rates(gpu_rates(torch, M, phi, p), ref.eval_rates(phi, p), mech, phi, p, "PaSR")
+    check_jac(gpu_jac(torch, M, phi, p), ref.eval_jacobian(phi, p), "PaSR")
+    c = conc_states(mech, phi, p)
+    out = M.eval_jacobian_conc(torch.from_numpy(c).cuda())
+    torch.cuda.synchronize()
+    colptr, rowidx = M.conc_pattern()
+    check_jac(densify(out.cpu().numpy(), colptr, rowidx, N), ref.eval_jacobian_conc(c), "PaSR conc")
+    r = ref.eval_rates(phi, p)
+    nf, nr = mech.stoich()
+    gross = np.abs(nr - nf) @ (np.abs(r["pres_mod"]) * (np.abs(r["rop_f"]) + np.abs(r["rop_r"])))
+    rel = np.linalg.norm(r["wdot"], axis=0) / np.maximum(np.linalg.norm(gross, axis=0), 1e-300)
+    print(f"C{cfg} PaSR: {phi.shape[1]} particles, T {phi[0].min():.0f}-{phi[0].max():.0f} K, "
+          f"|wdot|/gross median {np.median(rel):.2e}, min {rel.min():.2e}")
