@@ -203,6 +203,18 @@ pyjac_status pyjac_sdirk3_step(const pyjac_mech* mech, int64_t n_states, int64_t
                                double* phi_out, double* dnorm, void* workspace, size_t workspace_bytes,
                                void* stream);
 
+/* Complex-step Jacobian of the same constant-pressure RHS: column j of state
+ * s is Im f(Phi + i step e_j) / step, with every operation of the RHS
+ * (Sec. 2.1, Sec. 2.3 rate laws) in complex arithmetic and branch decisions
+ * on real parts.  Exact to rounding for any small step (no difference of
+ * nearby values), it is an accuracy reference of the kind Sec. 5.1 discusses,
+ * next to finite differences; it costs N complex RHS evaluations per state.
+ * Same arguments and layout as pyjac_eval_jacobian, plus step in (0, 1e-6]
+ * (1e-30 is typical).  Errors: as pyjac_eval_jacobian, PYJAC_E_UNSUPPORTED
+ * for more than 384 species. */
+pyjac_status pyjac_eval_jacobian_cs(const pyjac_mech* mech, int64_t n_states, int64_t ld, const double* phi,
+                                    const double* p, double step, double* jac, void* stream);
+
 /* Mixing fractional step of a partially stirred reactor (App. C): for every
  * particle s with partner q = partner[s] (0 <= q < n_states; a negative value
  * leaves s unchanged), the mixture enthalpy h and the mass fractions relax

@@ -137,6 +137,19 @@ class Mechanism:
         _lib.pyjac_eval_jacobian_conc(self._h, n, ld, phi_c.data_ptr(), out.data_ptr(), self._stream())
         return out
 
+    def eval_jacobian_cs(self, phi, p, step: float = 1e-30, out=None):
+        """Complex-step Jacobian of the RHS, same layout as eval_jacobian."""
+        torch = _torch()
+        n, ld = self._check_in(phi, p)
+        N = self.n_species
+        if out is None:
+            out = torch.empty((N * N, ld), dtype=torch.float64, device=phi.device)
+        elif out.shape[0] != N * N or out.stride(0) != ld or out.stride(1) != 1:
+            raise ValueError("out must be [N*N, ld] with the same ld as phi")
+        _lib.pyjac_eval_jacobian_cs(self._h, n, ld, phi.data_ptr(), p.data_ptr(), float(step), out.data_ptr(),
+                                    self._stream())
+        return out
+
     def eval_jacobian_fd(self, phi, p, out=None, chunk_states: int = 8192, workspace=None):
         """Forward-difference Jacobian (same layout as eval_jacobian)."""
         torch = _torch()

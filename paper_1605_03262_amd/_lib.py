@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "PYJAC_OK", -1: "PYJAC_E_INVALID", -2: "PYJAC_E_PARSE",
 # Every symbol include/pyjac.h declares.
 EXPORTED = ("pyjac_mech_load", "pyjac_mech_load_string", "pyjac_chemkin_to_text",
             "pyjac_mech_load_chemkin", "pyjac_mech_info", "pyjac_mech_free",
-            "pyjac_eval_rates", "pyjac_eval_jacobian", "pyjac_eval_jacobian_conc", "pyjac_conc_pattern", "pyjac_mix_pairs",
+            "pyjac_eval_rates", "pyjac_eval_jacobian", "pyjac_eval_jacobian_conc", "pyjac_conc_pattern", "pyjac_mix_pairs", "pyjac_eval_jacobian_cs",
             "pyjac_newton_workspace_bytes",
             "pyjac_newton_factor_solve", "pyjac_newton_factor_solve_noalloc", "pyjac_mech_set_variant", "pyjac_mech_get_variant",
             "pyjac_mech_autotune", "pyjac_fd_workspace_bytes", "pyjac_eval_jacobian_fd",
@@ -73,6 +73,8 @@ def load_library() -> ctypes.CDLL:
     lib.pyjac_conc_pattern.restype = st
     lib.pyjac_mix_pairs.argtypes = [vp, i64, i64, vp, vp, ctypes.c_double, vp, vp]
     lib.pyjac_mix_pairs.restype = st
+    lib.pyjac_eval_jacobian_cs.argtypes = [vp, i64, i64, vp, vp, ctypes.c_double, vp, vp]
+    lib.pyjac_eval_jacobian_cs.restype = st
     lib.pyjac_newton_workspace_bytes.argtypes = [vp, i64, i32]
     lib.pyjac_newton_workspace_bytes.restype = sz
     lib.pyjac_newton_factor_solve.argtypes = [vp, i64, i64, vp, vp, ctypes.c_double, vp, vp, i32,
@@ -197,6 +199,10 @@ def pyjac_conc_pattern(mech):
 
 def pyjac_mix_pairs(mech, n, ld, phi, partner, weight, phi_out, stream) -> None:
     check(load_library().pyjac_mix_pairs(mech, n, ld, phi, partner, weight, phi_out, stream), "pyjac_mix_pairs")
+
+
+def pyjac_eval_jacobian_cs(mech, n, ld, phi, p, step, jac, stream) -> None:
+    check(load_library().pyjac_eval_jacobian_cs(mech, n, ld, phi, p, step, jac, stream), "pyjac_eval_jacobian_cs")
 
 
 def pyjac_newton_workspace_bytes(mech, n, mode) -> int:

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(os.path.dirname(HERE), "_build", "obj")
 LIB = os.path.join(HERE, "libpyjac_mi355x.so")
-SOURCES = ["loader.cpp", "chemkin.cpp", "kinetics.hip", "sparse.hip", "newton.hip", "fd.hip",
+SOURCES = ["loader.cpp", "chemkin.cpp", "kinetics.hip", "newton.hip", "fd.hip", "cs.hip",
            "integ.hip", "serve.cpp", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -19,6 +19,8 @@ namespace pyjac {
 
 size_t tile_lds_bytes(int N, int NR, int NG, int TS, int NT, bool jac);
 size_t conc_lds_bytes(int N, int NR, int NG, int TS, int NT);
+hipError_t launch_cs_jacobian(const MechDev& md, int64_t n, int64_t ld, const double* phi, const double* p,
+                              double step, double* jac, hipStream_t st);
 hipError_t launch_mix_pairs(const MechDev& md, int64_t n, int64_t ld, const double* phi, const int* partner, double w,
                             double* out, hipStream_t st);
 hipError_t launch_conc(int TS, int NT, const MechDev& md, int64_t n, int64_t ld, const double* phi, double* out,
@@ -369,6 +371,20 @@ pyjac_status pyjac_eval_jacobian_conc(const pyjac_mech* m, int64_t n, int64_t ld
   const MechDev md = launch_view(m, v, true);
   hipError_t e = launch_conc(v.ts, v.nt, md, n, ld, phi_c, jac, lds, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("jacobian launch failed: ") + hipGetErrorString(e));
+  return PYJAC_OK;
+}
+
+pyjac_status pyjac_eval_jacobian_cs(const pyjac_mech* m, int64_t n, int64_t ld, const double* phi, const double* p,
+                                    double step, double* jac, void* stream) {
+  pyjac_status rc = check_common(m, n, ld, phi, p);
+  if (rc != PYJAC_OK) return rc;
+  if (n > 0 && !jac) return fail(PYJAC_E_INVALID, "jac is NULL");
+  if (misaligned(jac)) return fail(PYJAC_E_INVALID, "jac not 8-byte aligned");
+  if (!(step > 0.0) || !(step <= 1e-6)) return fail(PYJAC_E_INVALID, "step must lie in (0, 1e-6]");
+  if (m->host.N > 384) return fail(PYJAC_E_UNSUPPORTED, "complex-step Jacobian limited to 384 species");
+  if (n == 0) return PYJAC_OK;
+  hipError_t e = launch_cs_jacobian(m->dev, n, ld, phi, p, step, jac, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("complex-step launch failed: ") + hipGetErrorString(e));
   return PYJAC_OK;
 }
 
