@@ -133,6 +133,27 @@ pyjac_status pyjac_eval_rates(const pyjac_mech* mech, int64_t n_states, int64_t 
 pyjac_status pyjac_eval_jacobian(const pyjac_mech* mech, int64_t n_states, int64_t ld,
                                  const double* phi, const double* p, double* jac, void* stream);
 
+/* One batch of a multi-mechanism Jacobian launch. */
+typedef struct pyjac_work_item {
+  const pyjac_mech* mech;
+  int64_t n_states, ld;
+  const double* phi;   /* [N][ld] device */
+  const double* p;     /* [ld] device */
+  double* jac;         /* [N*N][ld] device */
+} pyjac_work_item;
+
+/* The Jacobians of several batches, possibly of different mechanisms, in one
+ * kernel launch (per state the same values, bitwise, as pyjac_eval_jacobian):
+ * the grid is a work list whose blocks map to (item, tile) pairs, each block
+ * reading its item's mechanism tables.  Every mechanism must currently use
+ * the same Jacobian launch shape (pyjac_mech_get_variant / set_variant) and
+ * column-stream form; the items go out in launches of at most 8.  The item
+ * array is read during the call (host memory, caller-owned); nothing is
+ * allocated or copied, so the launch can be captured into a HIP graph.
+ * Errors: as pyjac_eval_jacobian per item, PYJAC_E_UNSUPPORTED when the items
+ * do not share a launch shape; nothing is enqueued on an error. */
+pyjac_status pyjac_eval_jacobian_multi(int32_t n_items, const pyjac_work_item* items, void* stream);
+
 /* Sparse Jacobian of the concentration-based, constant-volume formulation
  * that Sec. 3.3 names as the route to Jacobian sparsity (concentrations as
  * state variables remove the density from the cross-species elements) and
@@ -334,20 +355,29 @@ pyjac_status pyjac_mech_get_variant(const pyjac_mech* mech, int32_t which, int32
                                     int32_t* threads, size_t* lds_bytes);
 
 /* ------------------------------------------------------------------------
- * Serving: continuous batching of Jacobian + Newton requests.
- * A server owns an HBM arena of hbm_budget_bytes on `device` and n_streams
- * streams.  Requests (host arrays, element-major with the request's own state
- * count as leading dimension: phi [N][n], p/h [n], rhs [N][n]; outputs x
- * [N][n], info [n]) are admitted in arrival order when their device footprint
- * fits the free arena; admitted requests with the same mechanism, mode and
- * gamma are packed into one batch of at most max_batch_states states and
- * evaluated (pyjac_eval_jacobian, then pyjac_newton_factor_solve with
- * max_refine/rtol) while other batches run on other streams.  A state's
- * result does not depend on the batch it lands in.  Inputs are copied into
- * pinned host staging memory (min(budget / 4, 2 GiB), at least 64 MiB) during
- * submit, which blocks while that memory is full; outputs are written to the
- * caller's x / info when the request completes, so those two arrays must stay
- * valid until pyjac_serve_wait has returned.
+ * Serving: continuous batching of Jacobian + Newton requests (the consumer of
+ * Sec. 1: many independent implicit steps asking for J and a Newton solve).
+ * A server owns n_streams streams on `device`; each stream holds resident
+ * slot pools per mechanism (states, Jacobians, Newton workspace) created at
+ * the mechanism's first request with capacity min(max_batch_states, what
+ * 90 % of the remaining hbm_budget_bytes holds across the streams).  Requests
+ * (host arrays, element-major with the request's own state count as leading
+ * dimension: phi [N][n], p/h [n], rhs [N][n]; outputs x [N][n], info [n])
+ * are taken in arrival order into rounds: the head request fixes the round's
+ * mode and gamma, later requests of any mechanism with the same mode and gamma
+ * join while each mechanism's share fits its pool.  A round copies its inputs
+ * into a free stream's pools, evaluates the Jacobians of all its mechanisms in
+ * one work-list launch per launch shape (pyjac_eval_jacobian_multi), solves
+ * each mechanism's Newton systems (pyjac_newton_factor_solve with
+ * max_refine/rtol) and copies the results out, while other rounds run on
+ * other streams.  Per mechanism a round computes its state count rounded up to
+ * 256 columns; the second round with the same kernel sequence on a stream is
+ * captured into a HIP graph, later ones replay it.  A state's result does not
+ * depend on the round it lands in.  Inputs are copied into pinned host
+ * staging memory (min(budget / 4, 2 GiB), at least 64 MiB) during submit,
+ * which blocks while that memory is full; outputs are written to the caller's
+ * x / info when the request completes, so those two arrays must stay valid
+ * until pyjac_serve_wait has returned.
  * ------------------------------------------------------------------------ */
 typedef struct pyjac_server pyjac_server;
 
@@ -357,8 +387,9 @@ pyjac_status pyjac_serve_create(int32_t device, size_t hbm_budget_bytes, int64_t
                                 int32_t n_streams, int32_t max_refine, double rtol,
                                 pyjac_server** out);
 
-/* Queues one request and returns its id at once.  Errors: PYJAC_E_INVALID,
- * PYJAC_E_NOMEM (footprint larger than the whole budget). */
+/* Queues one request and returns its id at once.  Errors: PYJAC_E_INVALID
+ * (n_states above max_batch_states, bad arguments, shutting down),
+ * PYJAC_E_NOMEM (the mechanism's pools cannot hold the request). */
 pyjac_status pyjac_serve_submit(pyjac_server* server, const pyjac_mech* mech, int64_t n_states,
                                 const double* phi, const double* p, const double* h,
                                 const double* rhs, double gamma, int32_t mode, double* x,
@@ -369,12 +400,20 @@ pyjac_status pyjac_serve_submit(pyjac_server* server, const pyjac_mech* mech, in
 pyjac_status pyjac_serve_wait(pyjac_server* server, uint64_t request_id, double timeout_s,
                               double* latency_s);
 
-/* Counters since creation and the p50/p99 latency of all completed requests. */
+/* Counters since creation and the p50/p99 latency of all completed requests;
+ * batches_done counts rounds, hbm_in_use the bytes of the resident pools. */
 pyjac_status pyjac_serve_stats(pyjac_server* server, int64_t* requests_done, int64_t* states_done,
                                int64_t* batches_done, double* p50_s, double* p99_s,
                                size_t* hbm_in_use);
 
-/* Completes every submitted request, then frees streams and arena. */
+/* Rounds run eagerly (first sighting of their kernel sequence, or capture
+ * refused), captured into a graph, and replayed from one; Jacobian launches
+ * and how many of them served more than one mechanism.  Any out may be NULL. */
+pyjac_status pyjac_serve_graph_stats(pyjac_server* server, int64_t* eager_rounds, int64_t* captured_rounds,
+                                     int64_t* replayed_rounds, int64_t* jacobian_launches,
+                                     int64_t* multi_mechanism_launches);
+
+/* Completes every submitted request, then frees graphs, pools and streams. */
 pyjac_status pyjac_serve_destroy(pyjac_server* server);
 
 /* Static description of a status code. */

@@ -244,9 +244,11 @@ class Mechanism:
 
 
 class Server:
-    """Continuous-batching server (C++ scheduler in the library): requests are
-    admitted by HBM footprint, packed per mechanism and run concurrently on
-    several streams.  submit() copies the inputs into pinned staging memory;
+    """Continuous-batching server (C++ scheduler in the library): requests of
+    any mechanism are packed into rounds that run concurrently on several
+    streams with resident per-mechanism pools, one Jacobian launch per launch
+    shape for all mechanisms of a round, and HIP-graph replay of repeated
+    rounds.  submit() copies the inputs into pinned staging memory;
     the output arrays it returns are filled when the request completes and
     are kept referenced here until wait() returns."""
 
@@ -286,6 +288,11 @@ class Server:
 
     def stats(self):
         return _lib.pyjac_serve_stats(self._h)
+
+    def graph_stats(self):
+        """Rounds run eagerly / captured / replayed, Jacobian launches and
+        launches that served several mechanisms."""
+        return _lib.pyjac_serve_graph_stats(self._h)
 
     def close(self) -> None:
         if getattr(self, "_h", None):

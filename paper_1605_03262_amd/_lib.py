@@ -21,13 +21,19 @@ STATUS_NAMES = {0: "PYJAC_OK", -1: "PYJAC_E_INVALID", -2: "PYJAC_E_PARSE",
 # Every symbol include/pyjac.h declares.
 EXPORTED = ("pyjac_mech_load", "pyjac_mech_load_string", "pyjac_chemkin_to_text",
             "pyjac_mech_load_chemkin", "pyjac_mech_info", "pyjac_mech_free",
-            "pyjac_eval_rates", "pyjac_eval_jacobian", "pyjac_eval_jacobian_conc", "pyjac_conc_pattern", "pyjac_mix_pairs", "pyjac_eval_jacobian_cs",
+            "pyjac_eval_rates", "pyjac_eval_jacobian", "pyjac_eval_jacobian_conc", "pyjac_conc_pattern", "pyjac_mix_pairs", "pyjac_eval_jacobian_cs", "pyjac_eval_jacobian_multi",
             "pyjac_newton_workspace_bytes",
             "pyjac_newton_factor_solve", "pyjac_newton_factor_solve_noalloc", "pyjac_mech_set_variant", "pyjac_mech_get_variant",
             "pyjac_mech_autotune", "pyjac_fd_workspace_bytes", "pyjac_eval_jacobian_fd",
             "pyjac_sdirk3_workspace_bytes", "pyjac_sdirk3_step",
             "pyjac_status_string", "pyjac_last_error", "pyjac_serve_create", "pyjac_serve_submit",
-            "pyjac_serve_wait", "pyjac_serve_stats", "pyjac_serve_destroy")
+            "pyjac_serve_wait", "pyjac_serve_stats", "pyjac_serve_graph_stats", "pyjac_serve_destroy")
+
+
+class WorkItem(ctypes.Structure):
+    """pyjac_work_item of include/pyjac.h."""
+    _fields_ = [("mech", ctypes.c_void_p), ("n_states", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("phi", ctypes.c_void_p), ("p", ctypes.c_void_p), ("jac", ctypes.c_void_p)]
 
 
 class PyjacError(RuntimeError):
@@ -75,6 +81,8 @@ def load_library() -> ctypes.CDLL:
     lib.pyjac_mix_pairs.restype = st
     lib.pyjac_eval_jacobian_cs.argtypes = [vp, i64, i64, vp, vp, ctypes.c_double, vp, vp]
     lib.pyjac_eval_jacobian_cs.restype = st
+    lib.pyjac_eval_jacobian_multi.argtypes = [i32, ctypes.POINTER(WorkItem), vp]
+    lib.pyjac_eval_jacobian_multi.restype = st
     lib.pyjac_newton_workspace_bytes.argtypes = [vp, i64, i32]
     lib.pyjac_newton_workspace_bytes.restype = sz
     lib.pyjac_newton_factor_solve.argtypes = [vp, i64, i64, vp, vp, ctypes.c_double, vp, vp, i32,
@@ -110,6 +118,8 @@ def load_library() -> ctypes.CDLL:
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(sz)]
     lib.pyjac_serve_stats.restype = st
+    lib.pyjac_serve_graph_stats.argtypes = [vp] + [ctypes.POINTER(i64)] * 5
+    lib.pyjac_serve_graph_stats.restype = st
     lib.pyjac_serve_destroy.argtypes = [vp]
     lib.pyjac_serve_destroy.restype = st
     lib.pyjac_status_string.argtypes = [st]
@@ -205,6 +215,12 @@ def pyjac_eval_jacobian_cs(mech, n, ld, phi, p, step, jac, stream) -> None:
     check(load_library().pyjac_eval_jacobian_cs(mech, n, ld, phi, p, step, jac, stream), "pyjac_eval_jacobian_cs")
 
 
+def pyjac_eval_jacobian_multi(items, stream) -> None:
+    """items: sequence of (mech, n_states, ld, phi, p, jac) tuples."""
+    arr = (WorkItem * max(len(items), 1))(*[WorkItem(*it) for it in items])
+    check(load_library().pyjac_eval_jacobian_multi(len(items), arr, stream), "pyjac_eval_jacobian_multi")
+
+
 def pyjac_newton_workspace_bytes(mech, n, mode) -> int:
     return int(load_library().pyjac_newton_workspace_bytes(mech, n, mode))
 
@@ -284,6 +300,13 @@ def pyjac_serve_stats(server):
           "pyjac_serve_stats")
     return {"requests": r.value, "states": s_.value, "batches": b.value, "p50_s": p50.value,
             "p99_s": p99.value, "hbm_in_use": use.value}
+
+
+def pyjac_serve_graph_stats(server):
+    v = [ctypes.c_int64() for _ in range(5)]
+    check(load_library().pyjac_serve_graph_stats(server, *[ctypes.byref(x) for x in v]), "pyjac_serve_graph_stats")
+    return dict(zip(("eager_rounds", "captured_rounds", "replayed_rounds", "jacobian_launches",
+                     "multi_mechanism_launches"), (x.value for x in v)))
 
 
 def pyjac_serve_destroy(server) -> None:

@@ -19,6 +19,8 @@ namespace pyjac {
 
 size_t tile_lds_bytes(int N, int NR, int NG, int TS, int NT, bool jac);
 size_t conc_lds_bytes(int N, int NR, int NG, int TS, int NT);
+hipError_t launch_tile_multi(int TS, int NT, int kpt, bool split, const WorkList& wl, int64_t tiles, size_t lds,
+                             hipStream_t st);
 hipError_t launch_cs_jacobian(const MechDev& md, int64_t n, int64_t ld, const double* phi, const double* p,
                               double step, double* jac, hipStream_t st);
 hipError_t launch_mix_pairs(const MechDev& md, int64_t n, int64_t ld, const double* phi, const int* partner, double w,
@@ -340,6 +342,58 @@ pyjac_status pyjac_eval_jacobian(const pyjac_mech* m, int64_t n, int64_t ld, con
   hipError_t e = launch_tile(true, v.ts, v.nt, md, n, ld, phi, p, nullptr, nullptr, nullptr, nullptr,
                              nullptr, jac, lds, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("jacobian launch failed: ") + hipGetErrorString(e));
+  return PYJAC_OK;
+}
+
+pyjac_status pyjac_eval_jacobian_multi(int32_t n_items, const pyjac_work_item* items, void* stream) {
+  if (n_items < 0 || (n_items > 0 && !items)) return fail(PYJAC_E_INVALID, "bad item list");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(PYJAC_E_DEVICE, "hipGetDevice failed");
+  // validate every item first, so that nothing is enqueued on an error
+  Variant v{0, 0};
+  int split = -1;
+  for (int32_t i = 0; i < n_items; ++i) {
+    const pyjac_work_item& it = items[i];
+    pyjac_status rc = check_common(it.mech, it.n_states, it.ld, it.phi, it.p);
+    if (rc != PYJAC_OK) return rc;
+    if (it.n_states > 0 && !it.jac) return fail(PYJAC_E_INVALID, "jac is NULL");
+    if (misaligned(it.jac)) return fail(PYJAC_E_INVALID, "jac not 8-byte aligned");
+    if (it.n_states == 0) continue;
+    const Variant w = it.mech->jac_var;
+    if (!v.ts) { v = w; split = it.mech->host.col_split; }
+    if (w.ts != v.ts || w.nt != v.nt || it.mech->host.col_split != split)
+      return fail(PYJAC_E_UNSUPPORTED, "items of one launch need the same Jacobian launch shape and stream form");
+  }
+  if (!v.ts) return PYJAC_OK;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int32_t i0 = 0; i0 < n_items;) {
+    WorkList wl{};
+    int64_t tiles = 0;
+    size_t lds = 0;
+    int kpt = 1;
+    int c = 0;
+    for (; i0 < n_items && c < kMaxWorkItems; ++i0) {
+      const pyjac_work_item& it = items[i0];
+      if (it.n_states == 0) continue;
+      const PackedMech& P = it.mech->host;
+      WorkItem& w = wl.item[c++];
+      w.md = launch_view(it.mech, v, true);
+      w.phi = it.phi;
+      w.p = it.p;
+      w.jac = it.jac;
+      w.n = it.n_states;
+      w.ld = it.ld;
+      w.tile0 = tiles;
+      tiles += (it.n_states + v.ts - 1) / v.ts;
+      lds = std::max(lds, tile_lds_bytes(P.N, P.NR, P.NG, v.ts, v.nt, true));
+      kpt = std::max(kpt, kpt_of(P.N, v.ts, v.nt));
+    }
+    if (!c) break;
+    wl.n_items = c;
+    if (tiles >= ((int64_t)1 << 31)) return fail(PYJAC_E_INVALID, "work list too large for one launch");
+    hipError_t e = launch_tile_multi(v.ts, v.nt, kpt, split == 1, wl, tiles, lds, st);
+    if (e != hipSuccess) return fail(PYJAC_E_DEVICE, std::string("work-list launch failed: ") + hipGetErrorString(e));
+  }
   return PYJAC_OK;
 }
 

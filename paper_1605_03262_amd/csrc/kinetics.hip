@@ -352,19 +352,19 @@ __device__ inline unsigned xcd_tile() {
 
 // SPLIT selects the form of the Jacobian column streams: every row streamed
 // (false) or only the rows with terms, the others written by a dense pass (true).
+// The body of one tile (states tile*TS .. tile*TS + TS - 1 of the batch).
 template <int TS, int NT, int KPT, bool JAC, bool SPLIT>
-__global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev md, int64_t n, int64_t ld,
-                                                  const double* __restrict__ phi,
-                                                  const double* __restrict__ pin,
-                                                  double* __restrict__ rop_f, double* __restrict__ rop_r,
-                                                  double* __restrict__ pmod, double* __restrict__ wdot_out,
-                                                  double* __restrict__ dphi_out, double* __restrict__ jac) {
+__device__ __forceinline__ void tile_body(const MechDev& md, unsigned tile, int64_t n, int64_t ld,
+                                          const double* __restrict__ phi, const double* __restrict__ pin,
+                                          double* __restrict__ rop_f, double* __restrict__ rop_r,
+                                          double* __restrict__ pmod, double* __restrict__ wdot_out,
+                                          double* __restrict__ dphi_out, double* __restrict__ jac) {
   constexpr int Gr = NT / TS;
   static_assert(Gr >= 3, "the per-state sums of phase C use three index groups");
   extern __shared__ double lds[];
   const int N = md.N, NR = md.NR, NG = md.NG;
   const int tid = threadIdx.x, s = tid % TS, g = tid / TS;
-  const int64_t sg = (int64_t)xcd_tile() * TS + s;
+  const int64_t sg = (int64_t)tile * TS + s;
   const bool live = sg < n;
   const int64_t sl = live ? sg : n - 1;
   const TileLayout L(N, NR, NG, Gr, JAC);
@@ -749,6 +749,32 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
   }
 }
 
+template <int TS, int NT, int KPT, bool JAC, bool SPLIT>
+__global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev md, int64_t n, int64_t ld,
+                                                  const double* __restrict__ phi,
+                                                  const double* __restrict__ pin,
+                                                  double* __restrict__ rop_f, double* __restrict__ rop_r,
+                                                  double* __restrict__ pmod, double* __restrict__ wdot_out,
+                                                  double* __restrict__ dphi_out, double* __restrict__ jac) {
+  tile_body<TS, NT, KPT, JAC, SPLIT>(md, xcd_tile(), n, ld, phi, pin, rop_f, rop_r, pmod, wdot_out, dphi_out, jac);
+}
+
+// ------------------------------------------------ multi-mechanism work list
+// One launch over the Jacobians of several batches, each with its own
+// mechanism tables, arrays and size: item i owns the tiles [tile0_i,
+// tile0_{i+1}) of the grid (every item shares the launch shape, the stream
+// form and an upper bound KPT of species per thread; the dynamic LDS is the
+// largest item's).  Per state the results are those of tile_kernel.
+template <int TS, int NT, int KPT, bool SPLIT>
+__global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_multi_kernel(WorkList wl) {
+  const unsigned t = xcd_tile();
+  int i = 0;
+  while (i + 1 < wl.n_items && (int64_t)t >= wl.item[i + 1].tile0) ++i;
+  const WorkItem& it = wl.item[i];
+  tile_body<TS, NT, KPT, true, SPLIT>(it.md, (unsigned)(t - it.tile0), it.n, it.ld, it.phi, it.p, nullptr, nullptr,
+                                      nullptr, nullptr, nullptr, it.jac);
+}
+
 // ---------------------------------------------- concentration-based Jacobian
 // State {T, [X_1..X_N]} of a constant-volume reactor (Sec. 3.3's sparse
 // formulation): d[X_k]/dt = wdot_k, dT/dt = -sum U_k wdot_k / sum [X_k] C_v,k
@@ -1115,6 +1141,41 @@ static hipError_t launch_conc_t(const MechDev& md, int64_t n, int64_t ld, const 
   const int64_t tiles = (n + TS - 1) / TS;
   hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(NT), lds, st, md, n, ld, phi, out);
   return hipGetLastError();
+}
+
+template <int TS, int NT, int KPT, bool SPLIT>
+static hipError_t launch_multi_t(const WorkList& wl, int64_t tiles, size_t lds, hipStream_t st) {
+  auto kern = tile_multi_kernel<TS, NT, KPT, SPLIT>;
+  hipError_t err = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(NT), lds, st, wl);
+  return hipGetLastError();
+}
+
+// Work-list Jacobian launch (see tile_multi_kernel); tiles = the grid size.
+hipError_t launch_tile_multi(int TS, int NT, int kpt, bool split, const WorkList& wl, int64_t tiles, size_t lds,
+                             hipStream_t st) {
+#define PYJAC_MULTI_K(ts, nt, k)                                                            \
+  if (kpt <= k) return split ? launch_multi_t<ts, nt, k, true>(wl, tiles, lds, st)          \
+                             : launch_multi_t<ts, nt, k, false>(wl, tiles, lds, st);
+#define PYJAC_MULTI(ts, nt)      \
+  if (TS == ts && NT == nt) {    \
+    PYJAC_MULTI_K(ts, nt, 1)     \
+    PYJAC_MULTI_K(ts, nt, 2)     \
+    PYJAC_MULTI_K(ts, nt, 4)     \
+    PYJAC_MULTI_K(ts, nt, 8)     \
+    return hipErrorInvalidValue; \
+  }
+  PYJAC_MULTI(16, 1024)
+  PYJAC_MULTI(8, 512)
+  PYJAC_MULTI(8, 1024)
+  PYJAC_MULTI(4, 512)
+  PYJAC_MULTI(4, 1024)
+  PYJAC_MULTI(2, 512)
+  PYJAC_MULTI(2, 1024)
+#undef PYJAC_MULTI
+#undef PYJAC_MULTI_K
+  return hipErrorInvalidValue;
 }
 
 // Concentration-form Jacobian launch; shapes (TS, NT) as listed in the body.

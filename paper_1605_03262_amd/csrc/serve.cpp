@@ -1,35 +1,35 @@
 // Continuous-batching server for Jacobian + Newton requests (host C++ side of
-// libpyjac_mi355x).
+// libpyjac_mi355x), on the scheduler core of sched.hpp.
 //
 // Requests (a mechanism, n states, step sizes and right-hand sides in host
-// memory) arrive at any time.  A scheduler thread admits them in arrival order
-// as device memory frees up: every request's device footprint is reserved from
-// a fixed arena whose size is the server's HBM budget, so a request that does
-// not fit waits (backpressure) and one larger than the budget is rejected at
-// submission.  Admitted requests of the same mechanism are packed side by side
-// into one batch (states are independent, so a state's result is the same in
-// any batch), copied in, evaluated with pyjac_eval_jacobian and
-// pyjac_newton_factor_solve on one of several streams, and copied out; a
-// completion thread releases the batch's memory when its stream reaches the
-// end and records each request's latency (completion - submission).
-// Batches on different streams run concurrently on the device, and new
-// requests are admitted while earlier batches are still running.
+// memory) arrive at any time; submit() copies the inputs into pinned staging
+// memory and queues them.  Rounds run on one of n_streams streams, each with
+// resident slot pools per mechanism (device arrays for states, Jacobians and
+// Newton workspace, sized at the mechanism's first request from the HBM
+// budget): a round places its requests side by side in its stream's pools,
+// copies the inputs in, evaluates every mechanism's Jacobian in one
+// work-list launch per launch shape (pyjac_eval_jacobian_multi), solves each
+// mechanism's Newton systems (pyjac_newton_factor_solve), and copies the
+// results out.  The pool extent a round computes is its mechanism's state
+// count rounded up to 256, so rounds repeat the same kernel sequence; the
+// second round with a given sequence (mode, gamma, per-mechanism extents) on a
+// stream captures it into a HIP graph and later ones replay it (the first runs
+// eagerly, which also sets every kernel attribute outside the capture).
+// Padding columns hold valid states from earlier rounds or the initial fill,
+// and states are independent, so a request's result is the same in any round.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
-#include <chrono>
-#include <condition_variable>
 #include <cstring>
-#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <string>
-#include <thread>
 #include <vector>
 
 #include "../../include/pyjac.h"
+#include "sched.hpp"
 
 namespace pyjac {
 pyjac_status fail(pyjac_status code, const std::string& msg);
@@ -39,43 +39,39 @@ int mech_species(const pyjac_mech* m);
 
 namespace {
 
-using Clock = std::chrono::steady_clock;
+constexpr int64_t kExtentQuantum = 256;   // a round's per-mechanism extent is a multiple of this
 
-// First-fit sub-allocator over one device allocation or one pinned host
-// allocation (256-byte granules).
-class Arena {
+size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// First-fit sub-allocator over one pinned host allocation (256-byte granules).
+class PinnedArena {
  public:
-  bool init(size_t bytes, bool pinned_host = false) {
-    size_ = (bytes + 255) & ~size_t(255);
-    host_ = pinned_host;
-    const hipError_t e = host_ ? hipHostMalloc(&base_, size_, hipHostMallocDefault) : hipMalloc(&base_, size_);
-    if (e != hipSuccess) {
+  bool init(size_t bytes) {
+    size_ = al256(bytes);
+    if (hipHostMalloc(&base_, size_, hipHostMallocDefault) != hipSuccess) {
       base_ = nullptr;
       return false;
     }
     free_[0] = size_;
     return true;
   }
-  ~Arena() {
-    if (base_) (host_ ? hipHostFree(base_) : hipFree(base_));
+  ~PinnedArena() {
+    if (base_) hipHostFree(base_);
   }
-  // returns offset or SIZE_MAX
   size_t take(size_t bytes) {
-    bytes = (bytes + 255) & ~size_t(255);
+    bytes = al256(bytes);
     for (auto it = free_.begin(); it != free_.end(); ++it) {
       if (it->second >= bytes) {
-        size_t off = it->first, len = it->second;
+        const size_t off = it->first, len = it->second;
         free_.erase(it);
         if (len > bytes) free_[off + bytes] = len - bytes;
-        used_ += bytes;
         return off;
       }
     }
     return SIZE_MAX;
   }
   void give(size_t off, size_t bytes) {
-    bytes = (bytes + 255) & ~size_t(255);
-    used_ -= bytes;
+    bytes = al256(bytes);
     auto it = free_.emplace(off, bytes).first;
     auto nx = std::next(it);
     if (nx != free_.end() && it->first + it->second == nx->first) { it->second += nx->second; free_.erase(nx); }
@@ -86,299 +82,286 @@ class Arena {
   }
   char* ptr(size_t off) const { return static_cast<char*>(base_) + off; }
   size_t size() const { return size_; }
-  size_t used() const { return used_; }
 
  private:
   void* base_ = nullptr;
-  bool host_ = false;
-  size_t size_ = 0, used_ = 0;
+  size_t size_ = 0;
   std::map<size_t, size_t> free_;
 };
 
-struct Request {
-  uint64_t id = 0;
-  const pyjac_mech* mech = nullptr;
-  int64_t n = 0;
-  int N = 0;
-  const double *phi = nullptr, *p = nullptr, *h = nullptr, *rhs = nullptr;
-  double gamma = 0;
-  int mode = 1;
-  double* x = nullptr;
-  int32_t* info = nullptr;
-  size_t bytes = 0;
-  // pinned staging slot: phi [N][n], p [n], h [n], rhs [N][n] in, x [N][n],
-  // info [n] out; the caller's arrays are only touched by submit (inputs)
-  // and by the completion thread (outputs)
-  size_t pin_off = 0, pin_bytes = 0;
-  char* pin = nullptr;
-  Clock::time_point t_submit, t_done;
-  bool done = false;
-  pyjac_status status = PYJAC_OK;
-};
-
-struct Batch {
-  std::vector<std::shared_ptr<Request>> reqs;
-  const pyjac_mech* mech = nullptr;
-  int64_t n = 0;
-  int N = 0;
-  size_t off = 0, bytes = 0;
-  int stream = 0;
-  hipEvent_t done_ev = nullptr;
-  bool launched = false;   // set under the lock once done_ev has been recorded
-};
-
+// Staging layout of one request: phi [N][n], p [n], h [n], rhs [N][n] in,
+// x [N][n], info [n] out.
 struct PinLayout {
   size_t phi, p, h, rhs, x, info, total;
 };
 PinLayout pin_layout(int N, int64_t n) {
-  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   PinLayout L;
   size_t o = 0;
-  L.phi = o; o += al((size_t)N * n * 8);
-  L.p = o; o += al((size_t)n * 8);
-  L.h = o; o += al((size_t)n * 8);
-  L.rhs = o; o += al((size_t)N * n * 8);
-  L.x = o; o += al((size_t)N * n * 8);
-  L.info = o; o += al((size_t)n * 4);
+  L.phi = o; o += al256((size_t)N * n * 8);
+  L.p = o; o += al256((size_t)n * 8);
+  L.h = o; o += al256((size_t)n * 8);
+  L.rhs = o; o += al256((size_t)N * n * 8);
+  L.x = o; o += al256((size_t)N * n * 8);
+  L.info = o; o += al256((size_t)n * 4);
   L.total = o;
   return L;
 }
 
-size_t request_bytes(int N, int64_t n, int mode) {
-  (void)mode;
-  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+struct Payload {
+  int N = 0;
+  double* x = nullptr;          // caller's output arrays
+  int32_t* info = nullptr;
+  size_t pin_off = 0, pin_bytes = 0;
+  char* pin = nullptr;
+  int64_t col = 0;              // first column in the round's pool (set at launch)
+};
+
+// Resident device arrays of one mechanism on one stream, capacity C states.
+struct Pool {
+  int64_t C = 0;
+  void* mem = nullptr;
+  size_t bytes = 0, wsb = 0;
+  double *phi = nullptr, *p = nullptr, *h = nullptr, *rhs = nullptr, *x = nullptr, *jac = nullptr;
+  int32_t* info = nullptr;
+  void* ws = nullptr;
+};
+
+size_t pool_bytes(const pyjac_mech* m, int64_t C) {
+  const int N = pyjac::mech_species(m);
   size_t b = 0;
-  b += al((size_t)N * n * 8);               // phi
-  b += al((size_t)n * 8) * 2;               // p, h
-  b += al((size_t)N * n * 8) * 2;           // rhs, x
-  b += al((size_t)n * 4);                   // info
-  b += al((size_t)N * N * n * 8);           // jac
+  b += al256((size_t)N * C * 8) * 3;         // phi, rhs, x
+  b += al256((size_t)C * 8) * 2;             // p, h
+  b += al256((size_t)C * 4);                 // info
+  b += al256((size_t)N * N * C * 8);         // jac
+  b += al256(std::max(pyjac_newton_workspace_bytes(m, C, 0), pyjac_newton_workspace_bytes(m, C, 1)));
   return b;
 }
 
+struct GraphEntry {
+  int seen = 0;
+  bool no_graph = false;
+  hipGraphExec_t exec = nullptr;
+};
+
 }  // namespace
 
-struct pyjac_server {
+struct pyjac_server : public pyjac::sched::Executor {
   int device = 0;
-  int n_streams = 2;
+  int n_streams_ = 1;
   int64_t max_batch = 4096;
   int max_refine = 4;
   double rtol = 1e-14;
-  Arena arena;                 // device memory of admitted batches
-  Arena pinned;                // host staging of submitted requests
+  size_t budget = 0;
   std::vector<hipStream_t> streams;
-  std::vector<int> stream_busy;
-
-  std::mutex mu;
-  std::condition_variable cv_sched, cv_done, cv_pin;
-  std::deque<std::shared_ptr<Request>> pending;
-  std::map<uint64_t, std::shared_ptr<Request>> all;
-  std::deque<std::unique_ptr<Batch>> inflight;
-  std::vector<double> latencies;
-  uint64_t next_id = 1;
-  int64_t states_done = 0, batches_done = 0, requests_done = 0;
-  bool stop = false;
+  std::vector<hipEvent_t> events;
+  PinnedArena pinned;
+  std::mutex pin_mu;
+  std::condition_variable cv_pin;
+  bool closing = false;
+  // mechanism registry and pools (pools[slot][key]); a slot's pools and graphs
+  // are touched only by the round running on it
+  mutable std::mutex reg_mu;
+  std::vector<const pyjac_mech*> mechs;
+  std::vector<int64_t> cap;                            // per key
+  std::vector<std::map<int, Pool>> pools;
+  std::vector<std::map<std::string, GraphEntry>> graphs;
+  size_t pool_total = 0;
+  std::atomic<int64_t> n_eager{0}, n_captured{0}, n_replayed{0}, n_jac_launches{0}, n_multi_mech{0};
+  std::mutex err_mu;
   std::string error;
-  std::thread sched, reaper;
+  std::unique_ptr<pyjac::sched::Scheduler> sch;
+
+  // ---- Executor
+  int n_slots() const override { return n_streams_; }
+  int64_t capacity(int key) const override {
+    std::lock_guard<std::mutex> g(reg_mu);
+    return cap[key];
+  }
+  int launch(pyjac::sched::Round& R) override;
+  bool poll(pyjac::sched::Round& R) override { return hipEventQuery(events[R.slot]) != hipErrorNotReady; }
+  void finish(pyjac::sched::Round& R) override;
+
+  void set_error(const std::string& s) {
+    std::lock_guard<std::mutex> g(err_mu);
+    error = s;
+  }
+  const pyjac_mech* mech_of(int key) const {
+    std::lock_guard<std::mutex> g(reg_mu);
+    return mechs[key];
+  }
+  int compute(pyjac::sched::Round& R, const std::vector<std::pair<int, int64_t>>& extents);
 };
 
 namespace {
 
-size_t batch_bytes(const pyjac_mech* m, int N, int64_t n, int mode) {
-  return request_bytes(N, n, mode) + ((pyjac_newton_workspace_bytes(m, n, mode) + 255) & ~size_t(255));
-}
-
-// Launch one batch on its stream (called with the lock released).
-pyjac_status launch_batch(pyjac_server* S, Batch& B) {
-  hipStream_t st = S->streams[B.stream];
-  const int N = B.N;
-  const int64_t n = B.n;
-  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  char* base = S->arena.ptr(B.off);
-  size_t o = 0;
-  double* phi = reinterpret_cast<double*>(base + o); o += al((size_t)N * n * 8);
-  double* p = reinterpret_cast<double*>(base + o); o += al((size_t)n * 8);
-  double* h = reinterpret_cast<double*>(base + o); o += al((size_t)n * 8);
-  double* rhs = reinterpret_cast<double*>(base + o); o += al((size_t)N * n * 8);
-  double* x = reinterpret_cast<double*>(base + o); o += al((size_t)N * n * 8);
-  int32_t* info = reinterpret_cast<int32_t*>(base + o); o += al((size_t)n * 4);
-  double* jac = reinterpret_cast<double*>(base + o); o += al((size_t)N * N * n * 8);
-  void* ws = base + o;
-  const int mode = B.reqs.front()->mode;
-  const double gamma = B.reqs.front()->gamma;
-  const size_t wsb = pyjac_newton_workspace_bytes(B.mech, n, mode);
-  int64_t col = 0;
-  for (auto& r : B.reqs) {
-    const size_t w = (size_t)r->n * 8;
-    const PinLayout P = pin_layout(N, r->n);
-    if (hipMemcpy2DAsync(phi + col, n * 8, r->pin + P.phi, w, w, N, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(p + col, r->pin + P.p, w, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(h + col, r->pin + P.h, w, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpy2DAsync(rhs + col, n * 8, r->pin + P.rhs, w, w, N, hipMemcpyHostToDevice, st) != hipSuccess)
-      return pyjac::fail(PYJAC_E_DEVICE, "request copy-in failed");
-    col += r->n;
-  }
-  pyjac_status rc = pyjac_eval_jacobian(B.mech, n, n, phi, p, jac, st);
-  if (rc == PYJAC_OK)
-    rc = pyjac_newton_factor_solve(B.mech, n, n, jac, h, gamma, rhs, x, mode, S->max_refine, S->rtol, info, ws,
-                                   wsb, st);
-  if (rc != PYJAC_OK) return rc;
-  col = 0;
-  for (auto& r : B.reqs) {
-    const size_t w = (size_t)r->n * 8;
-    const PinLayout P = pin_layout(N, r->n);
-    if (hipMemcpy2DAsync(r->pin + P.x, w, x + col, n * 8, w, N, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipMemcpyAsync(r->pin + P.info, info + col, (size_t)r->n * 4, hipMemcpyDeviceToHost, st) != hipSuccess)
-      return pyjac::fail(PYJAC_E_DEVICE, "request copy-out failed");
-    col += r->n;
-  }
-  if (hipEventRecord(B.done_ev, st) != hipSuccess) return pyjac::fail(PYJAC_E_DEVICE, "event record failed");
+// Fills a new pool with valid states (T 1500 K, equal mass fractions, 1 atm,
+// h = 0 so that A = I), so that padding columns never hold garbage.
+pyjac_status init_pool(const pyjac_mech* m, Pool& P) {
+  const int N = pyjac::mech_species(m);
+  const int64_t C = P.C;
+  std::vector<double> col((size_t)N * C);
+  for (int64_t s = 0; s < C; ++s) col[s] = 1500.0;
+  for (int k = 1; k < N; ++k)
+    for (int64_t s = 0; s < C; ++s) col[(size_t)k * C + s] = 1.0 / N;
+  std::vector<double> pv(C, 101325.0), zero((size_t)N * C, 0.0);
+  if (hipMemcpy(P.phi, col.data(), col.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(P.p, pv.data(), C * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(P.h, zero.data(), C * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(P.rhs, zero.data(), zero.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+    return pyjac::fail(PYJAC_E_DEVICE, "pool initialization failed");
   return PYJAC_OK;
 }
 
-void scheduler_loop(pyjac_server* S) {
-  hipSetDevice(S->device);
-  std::unique_lock<std::mutex> lk(S->mu);
-  while (true) {
-    // Wake for a pending request once a stream is free, or to exit once a
-    // stop has been requested and nothing is pending.  Pending requests keep
-    // the loop alive after a stop; it then still waits (releasing the lock)
-    // until the completion thread frees a stream.
-    S->cv_sched.wait(lk, [&] {
-      if (S->pending.empty()) return S->stop;
-      for (int b : S->stream_busy) if (!b) return true;
-      return false;
-    });
-    if (S->pending.empty()) break;
-    int sidx = -1;
-    for (int i = 0; i < S->n_streams; ++i) if (!S->stream_busy[i]) { sidx = i; break; }
-    // Form a batch: the head request's mechanism and mode, then later requests
-    // with the same mechanism/mode, in arrival order, while the packed batch
-    // stays within max_batch states and fits the free arena.
-    auto head = S->pending.front();
-    auto B = std::make_unique<Batch>();
-    B->mech = head->mech;
-    B->N = head->N;
-    int64_t n = 0;
-    std::vector<size_t> pick;
-    for (size_t q = 0; q < S->pending.size(); ++q) {
-      auto& r = S->pending[q];
-      if (r->mech != head->mech || r->mode != head->mode || r->gamma != head->gamma) continue;
-      if (n > 0 && n + r->n > S->max_batch) break;
-      n += r->n;
-      pick.push_back(q);
-    }
-    size_t need = batch_bytes(B->mech, B->N, n, head->mode);
-    size_t off = S->arena.take(need);
-    while (off == SIZE_MAX && pick.size() > 1) {   // shrink to what fits
-      n -= S->pending[pick.back()]->n;
-      pick.pop_back();
-      need = batch_bytes(B->mech, B->N, n, head->mode);
-      off = S->arena.take(need);
-    }
-    if (off == SIZE_MAX) {                          // head waits for memory (backpressure)
-      S->cv_sched.wait_for(lk, std::chrono::milliseconds(2));
-      continue;
-    }
-    for (auto it = pick.rbegin(); it != pick.rend(); ++it) {
-      B->reqs.insert(B->reqs.begin(), S->pending[*it]);
-      S->pending.erase(S->pending.begin() + *it);
-    }
-    B->n = n;
-    B->off = off;
-    B->bytes = need;
-    B->stream = sidx;
-    S->stream_busy[sidx] = 1;
-    hipEventCreateWithFlags(&B->done_ev, hipEventDisableTiming);
-    Batch* raw = B.get();
-    S->inflight.push_back(std::move(B));
-    lk.unlock();
-    pyjac_status rc = launch_batch(S, *raw);
-    if (rc != PYJAC_OK) {
-      hipStreamSynchronize(S->streams[raw->stream]);
-      hipEventRecord(raw->done_ev, S->streams[raw->stream]);
-    }
-    lk.lock();
-    if (rc != PYJAC_OK) {
-      S->error = pyjac_last_error();
-      for (auto& r : raw->reqs) r->status = rc;
-    }
-    // Only now may the completion thread look at the batch: an event that was
-    // never recorded reads as complete.
-    raw->launched = true;
-    S->cv_done.notify_all();
-  }
-}
-
-void reaper_loop(pyjac_server* S) {
-  hipSetDevice(S->device);
-  std::unique_lock<std::mutex> lk(S->mu);
-  while (true) {
-    if (S->inflight.empty()) {
-      if (S->stop && S->pending.empty()) break;
-      S->cv_done.wait_for(lk, std::chrono::milliseconds(5));
-      continue;
-    }
-    // Snapshot the launched batches under the lock and query their events
-    // without it.  Only this thread erases from `inflight`, so the pointers
-    // stay valid while the scheduler appends new batches.
-    std::vector<Batch*> snap;
-    for (auto& b : S->inflight)
-      if (b->launched) snap.push_back(b.get());
-    std::vector<hipError_t> st(snap.size());
-    lk.unlock();
-    for (size_t q = 0; q < snap.size(); ++q) st[q] = hipEventQuery(snap[q]->done_ev);
-    lk.lock();
-    // results of the finished batches go from the pinned slots to the
-    // callers' arrays without the lock (the requests are not done yet, so
-    // nobody else touches those slots)
-    lk.unlock();
-    for (size_t q = 0; q < snap.size(); ++q) {
-      if (st[q] != hipSuccess) continue;
-      for (auto& r : snap[q]->reqs) {
-        const PinLayout P = pin_layout(r->N, r->n);
-        std::memcpy(r->x, r->pin + P.x, (size_t)r->N * r->n * 8);
-        std::memcpy(r->info, r->pin + P.info, (size_t)r->n * 4);
-      }
-    }
-    lk.lock();
-    bool any = false;
-    for (size_t q = 0; q < snap.size(); ++q) {
-      if (st[q] == hipErrorNotReady) continue;
-      Batch* B = snap[q];
-      const hipError_t qs = st[q];
-      const auto now = Clock::now();
-      for (auto& r : B->reqs) {
-        S->pinned.give(r->pin_off, r->pin_bytes);
-        r->pin = nullptr;
-        r->t_done = now;
-        r->done = true;
-        if (qs != hipSuccess && r->status == PYJAC_OK) r->status = PYJAC_E_DEVICE;
-        S->latencies.push_back(std::chrono::duration<double>(r->t_done - r->t_submit).count());
-        S->requests_done += 1;
-      }
-      S->states_done += B->n;
-      S->batches_done += 1;
-      S->arena.give(B->off, B->bytes);
-      S->stream_busy[B->stream] = 0;
-      hipEventDestroy(B->done_ev);
-      for (auto it = S->inflight.begin(); it != S->inflight.end(); ++it)
-        if (it->get() == B) { S->inflight.erase(it); break; }
-      any = true;
-    }
-    if (any) {
-      S->cv_sched.notify_all();
-      S->cv_done.notify_all();
-      S->cv_pin.notify_all();
-    } else {
-      lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(50));
-      lk.lock();
-    }
-  }
-}
-
 }  // namespace
+
+int pyjac_server::compute(pyjac::sched::Round& R, const std::vector<std::pair<int, int64_t>>& extents) {
+  hipStream_t st = streams[R.slot];
+  auto& pl = pools[R.slot];
+  // Jacobians: one work-list launch per launch shape over the round's mechanisms
+  std::map<std::pair<int, int>, std::vector<pyjac_work_item>> groups;
+  for (auto& [key, E] : extents) {
+    const pyjac_mech* m = mech_of(key);
+    const Pool& P = pl.at(key);
+    int32_t ts = 0, nt = 0;
+    pyjac_mech_get_variant(m, 1, &ts, &nt, nullptr);
+    groups[{ts, nt}].push_back(pyjac_work_item{m, E, P.C, P.phi, P.p, P.jac});
+  }
+  for (auto& [shape, items] : groups) {
+    pyjac_status rc = pyjac_eval_jacobian_multi((int32_t)items.size(), items.data(), st);
+    if (rc == PYJAC_E_UNSUPPORTED) {      // different column-stream forms: one launch per mechanism
+      for (auto& it : items) {
+        rc = pyjac_eval_jacobian_multi(1, &it, st);
+        if (rc != PYJAC_OK) break;
+        n_jac_launches += 1;
+      }
+    } else if (rc == PYJAC_OK) {
+      n_jac_launches += (int64_t)(items.size() + 7) / 8;
+      if (items.size() > 1) n_multi_mech += 1;
+    }
+    if (rc != PYJAC_OK) return rc;
+  }
+  for (auto& [key, E] : extents) {
+    const pyjac_mech* m = mech_of(key);
+    const Pool& P = pl.at(key);
+    pyjac_status rc = pyjac_newton_factor_solve(m, E, P.C, P.jac, P.h, R.gamma, P.rhs, P.x, R.mode, max_refine, rtol,
+                                                P.info, P.ws, P.wsb, st);
+    if (rc != PYJAC_OK) return rc;
+  }
+  return PYJAC_OK;
+}
+
+int pyjac_server::launch(pyjac::sched::Round& R) {
+  hipSetDevice(device);
+  hipStream_t st = streams[R.slot];
+  auto& pl = pools[R.slot];
+  // place the requests side by side per mechanism and copy their inputs in
+  std::vector<std::pair<int, int64_t>> extents;
+  for (size_t q = 0; q < R.reqs.size();) {
+    const int key = R.reqs[q]->mech;
+    const Pool& P = pl.at(key);
+    int64_t col = 0;
+    for (; q < R.reqs.size() && R.reqs[q]->mech == key; ++q) {
+      auto* pay = static_cast<Payload*>(R.reqs[q]->payload);
+      const int64_t n = R.reqs[q]->n;
+      const int N = pay->N;
+      const PinLayout L = pin_layout(N, n);
+      const size_t w = (size_t)n * 8;
+      pay->col = col;
+      if (hipMemcpy2DAsync(P.phi + col, P.C * 8, pay->pin + L.phi, w, w, N, hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipMemcpyAsync(P.p + col, pay->pin + L.p, w, hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipMemcpyAsync(P.h + col, pay->pin + L.h, w, hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipMemcpy2DAsync(P.rhs + col, P.C * 8, pay->pin + L.rhs, w, w, N, hipMemcpyHostToDevice, st) != hipSuccess) {
+        set_error("request copy-in failed");
+        return PYJAC_E_DEVICE;
+      }
+      col += n;
+    }
+    extents.push_back({key, std::min(P.C, (col + kExtentQuantum - 1) / kExtentQuantum * kExtentQuantum)});
+  }
+  // the round's kernel sequence: eager the first time, captured the second,
+  // replayed afterwards
+  std::string sig = std::to_string(R.mode) + "/";
+  sig.append(reinterpret_cast<const char*>(&R.gamma), sizeof(double));
+  for (auto& [key, E] : extents) sig += "/" + std::to_string(key) + ":" + std::to_string(E);
+  GraphEntry& G = graphs[R.slot][sig];
+  int rc = PYJAC_OK;
+  if (G.exec) {
+    if (hipGraphLaunch(G.exec, st) != hipSuccess) {
+      set_error("graph launch failed");
+      return PYJAC_E_DEVICE;
+    }
+    n_replayed += 1;
+  } else if (G.seen == 0 || G.no_graph) {
+    rc = compute(R, extents);
+    G.seen += 1;
+    n_eager += 1;
+  } else {
+    hipGraph_t graph = nullptr;
+    bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      rc = compute(R, extents);
+      const bool ended = hipStreamEndCapture(st, &graph) == hipSuccess;
+      ok = ended && rc == PYJAC_OK && graph;
+    }
+    if (ok) ok = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) hipGraphDestroy(graph);
+    if (ok) ok = hipGraphLaunch(G.exec, st) == hipSuccess;
+    if (ok) {
+      n_captured += 1;
+    } else {
+      // capture refused: run this and later rounds of the sequence eagerly
+      if (G.exec) {
+        hipGraphExecDestroy(G.exec);
+        G.exec = nullptr;
+      }
+      G.no_graph = true;
+      hipGetLastError();
+      rc = compute(R, extents);
+      n_eager += 1;
+    }
+  }
+  if (rc != PYJAC_OK) {
+    set_error(pyjac_last_error());
+    return rc;
+  }
+  // results out
+  for (auto& r : R.reqs) {
+    auto* pay = static_cast<Payload*>(r->payload);
+    const Pool& P = pl.at(r->mech);
+    const PinLayout L = pin_layout(pay->N, r->n);
+    const size_t w = (size_t)r->n * 8;
+    if (hipMemcpy2DAsync(pay->pin + L.x, w, P.x + pay->col, P.C * 8, w, pay->N, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(pay->pin + L.info, P.info + pay->col, (size_t)r->n * 4, hipMemcpyDeviceToHost, st) !=
+            hipSuccess) {
+      set_error("request copy-out failed");
+      return PYJAC_E_DEVICE;
+    }
+  }
+  if (hipEventRecord(events[R.slot], st) != hipSuccess) {
+    set_error("event record failed");
+    return PYJAC_E_DEVICE;
+  }
+  return PYJAC_OK;
+}
+
+void pyjac_server::finish(pyjac::sched::Round& R) {
+  const bool dev_ok = hipEventQuery(events[R.slot]) == hipSuccess;
+  for (auto& r : R.reqs) {
+    auto* pay = static_cast<Payload*>(r->payload);
+    const PinLayout L = pin_layout(pay->N, r->n);
+    std::memcpy(pay->x, pay->pin + L.x, (size_t)pay->N * r->n * 8);
+    std::memcpy(pay->info, pay->pin + L.info, (size_t)r->n * 4);
+    if (!dev_ok) r->status = PYJAC_E_DEVICE;
+  }
+  std::lock_guard<std::mutex> g(pin_mu);
+  for (auto& r : R.reqs) {
+    auto* pay = static_cast<Payload*>(r->payload);
+    pinned.give(pay->pin_off, pay->pin_bytes);
+    pay->pin = nullptr;
+  }
+  cv_pin.notify_all();
+}
 
 extern "C" {
 
@@ -391,35 +374,35 @@ pyjac_status pyjac_serve_create(int32_t device, size_t hbm_budget_bytes, int64_t
     return pyjac::fail(PYJAC_E_INVALID, "bad server parameters");
   auto S = std::make_unique<pyjac_server>();
   S->device = device;
-  S->n_streams = n_streams;
+  S->n_streams_ = n_streams;
   S->max_batch = max_batch_states;
   S->max_refine = max_refine;
   S->rtol = rtol;
+  S->budget = hbm_budget_bytes;
   int prev = 0;
   hipGetDevice(&prev);
   if (hipSetDevice(device) != hipSuccess) return pyjac::fail(PYJAC_E_DEVICE, "no such device");
-  if (!S->arena.init(hbm_budget_bytes)) {
-    hipSetDevice(prev);
-    return pyjac::fail(PYJAC_E_NOMEM, "cannot reserve the HBM budget");
-  }
   const size_t pin_bytes = std::max<size_t>(64u << 20, std::min<size_t>(hbm_budget_bytes / 4, size_t(2) << 30));
-  if (!S->pinned.init(pin_bytes, true)) {
+  if (!S->pinned.init(pin_bytes)) {
     hipSetDevice(prev);
     return pyjac::fail(PYJAC_E_NOMEM, "cannot allocate pinned host staging memory");
   }
   for (int i = 0; i < n_streams; ++i) {
     hipStream_t st;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    hipEvent_t ev;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
       hipSetDevice(prev);
       return pyjac::fail(PYJAC_E_DEVICE, "stream creation failed");
     }
     S->streams.push_back(st);
+    S->events.push_back(ev);
   }
-  S->stream_busy.assign(n_streams, 0);
+  S->pools.resize(n_streams);
+  S->graphs.resize(n_streams);
   hipSetDevice(prev);
   pyjac_server* raw = S.release();
-  raw->sched = std::thread(scheduler_loop, raw);
-  raw->reaper = std::thread(reaper_loop, raw);
+  raw->sch = std::make_unique<pyjac::sched::Scheduler>(raw, INT64_MAX / 4);
   *out = raw;
   return PYJAC_OK;
 }
@@ -432,46 +415,112 @@ pyjac_status pyjac_serve_submit(pyjac_server* S, const pyjac_mech* mech, int64_t
   if (!phi || !p || !h || !rhs || !x || !info) return pyjac::fail(PYJAC_E_INVALID, "NULL array");
   if (mode != 0 && mode != 1) return pyjac::fail(PYJAC_E_INVALID, "mode must be 0 or 1");
   if (pyjac::mech_device(mech) != S->device) return pyjac::fail(PYJAC_E_INVALID, "mechanism on another device");
-  auto r = std::make_shared<Request>();
-  r->mech = mech;
-  r->n = n_states;
-  r->N = pyjac::mech_species(mech);
-  r->phi = phi; r->p = p; r->h = h; r->rhs = rhs;
-  r->gamma = gamma;
-  r->mode = mode;
-  r->x = x;
-  r->info = info;
-  r->bytes = batch_bytes(mech, r->N, n_states, mode);
-  if (r->bytes > S->arena.size()) return pyjac::fail(PYJAC_E_NOMEM, "request larger than the server's HBM budget");
   if (n_states > S->max_batch) return pyjac::fail(PYJAC_E_INVALID, "request larger than max_batch_states");
-  const PinLayout P = pin_layout(r->N, n_states);
-  r->pin_bytes = P.total;
-  if (P.total > S->pinned.size()) return pyjac::fail(PYJAC_E_NOMEM, "request larger than the pinned staging memory");
-  const auto t0 = Clock::now();
-  std::unique_lock<std::mutex> lk(S->mu);
-  // backpressure on the submitting thread while the staging memory is full
-  size_t off = SIZE_MAX;
-  while (!S->stop && (off = S->pinned.take(P.total)) == SIZE_MAX) S->cv_pin.wait(lk);
-  if (S->stop) {
-    if (off != SIZE_MAX) S->pinned.give(off, P.total);
+  const int N = pyjac::mech_species(mech);
+  // the mechanism's pools: at its first request, one per stream, of capacity
+  // min(max_batch_states, what 90 % of the remaining budget holds)
+  int key = -1;
+  {
+    std::lock_guard<std::mutex> g(S->reg_mu);
+    for (size_t k = 0; k < S->mechs.size(); ++k)
+      if (S->mechs[k] == mech) key = (int)k;
+    if (key < 0) {
+      const size_t per = pool_bytes(mech, kExtentQuantum) / kExtentQuantum + 1;
+      const size_t room = S->budget > S->pool_total ? (size_t)(0.9 * (double)(S->budget - S->pool_total)) : 0;
+      const int64_t fit = (int64_t)(room / ((size_t)S->n_streams_ * per));
+      int64_t C = std::min<int64_t>(S->max_batch, fit);
+      if (C >= kExtentQuantum) C = C / kExtentQuantum * kExtentQuantum;
+      if (C < n_states) return pyjac::fail(PYJAC_E_NOMEM, "request larger than the server's HBM budget holds");
+      int prev = 0;
+      hipGetDevice(&prev);
+      hipSetDevice(S->device);
+      std::vector<Pool> made;
+      pyjac_status rc = PYJAC_OK;
+      for (int sl = 0; sl < S->n_streams_ && rc == PYJAC_OK; ++sl) {
+        Pool P;
+        P.C = C;
+        P.bytes = pool_bytes(mech, C);
+        if (hipMalloc(&P.mem, P.bytes) != hipSuccess) {
+          rc = pyjac::fail(PYJAC_E_NOMEM, "pool allocation failed");
+          break;
+        }
+        char* b = static_cast<char*>(P.mem);
+        size_t o = 0;
+        auto take = [&](size_t bytes) {
+          char* q = b + o;
+          o += al256(bytes);
+          return q;
+        };
+        P.phi = reinterpret_cast<double*>(take((size_t)N * C * 8));
+        P.rhs = reinterpret_cast<double*>(take((size_t)N * C * 8));
+        P.x = reinterpret_cast<double*>(take((size_t)N * C * 8));
+        P.p = reinterpret_cast<double*>(take((size_t)C * 8));
+        P.h = reinterpret_cast<double*>(take((size_t)C * 8));
+        P.info = reinterpret_cast<int32_t*>(take((size_t)C * 4));
+        P.jac = reinterpret_cast<double*>(take((size_t)N * N * C * 8));
+        P.wsb = std::max(pyjac_newton_workspace_bytes(mech, C, 0), pyjac_newton_workspace_bytes(mech, C, 1));
+        P.ws = take(P.wsb);
+        made.push_back(P);
+        rc = init_pool(mech, made.back());
+      }
+      hipSetDevice(prev);
+      if (rc != PYJAC_OK) {
+        for (auto& P : made)
+          if (P.mem) hipFree(P.mem);
+        return rc;
+      }
+      key = (int)S->mechs.size();
+      S->mechs.push_back(mech);
+      S->cap.push_back(C);
+      for (int sl = 0; sl < S->n_streams_; ++sl) {
+        S->pools[sl][key] = made[sl];
+        S->pool_total += made[sl].bytes;
+      }
+    } else if (n_states > S->cap[key]) {
+      return pyjac::fail(PYJAC_E_NOMEM, "request larger than the mechanism's pool");
+    }
+  }
+  const PinLayout L = pin_layout(N, n_states);
+  if (L.total > S->pinned.size()) return pyjac::fail(PYJAC_E_NOMEM, "request larger than the pinned staging memory");
+  auto pay = std::make_unique<Payload>();
+  pay->N = N;
+  pay->x = x;
+  pay->info = info;
+  pay->pin_bytes = L.total;
+  {
+    // backpressure on the submitting thread while the staging memory is full
+    std::unique_lock<std::mutex> lk(S->pin_mu);
+    size_t off = SIZE_MAX;
+    while (!S->closing && (off = S->pinned.take(L.total)) == SIZE_MAX) S->cv_pin.wait(lk);
+    if (S->closing) {
+      if (off != SIZE_MAX) S->pinned.give(off, L.total);
+      return pyjac::fail(PYJAC_E_INVALID, "server is shutting down");
+    }
+    pay->pin_off = off;
+    pay->pin = S->pinned.ptr(off);
+  }
+  const size_t w = (size_t)n_states * 8;
+  std::memcpy(pay->pin + L.phi, phi, (size_t)N * w);
+  std::memcpy(pay->pin + L.p, p, w);
+  std::memcpy(pay->pin + L.h, h, w);
+  std::memcpy(pay->pin + L.rhs, rhs, (size_t)N * w);
+  auto r = std::make_shared<pyjac::sched::Request>();
+  r->mech = key;
+  r->n = n_states;
+  r->mode = mode;
+  r->gamma = gamma;
+  r->payload = pay.release();
+  const uint64_t id = S->sch->submit(r);
+  if (!id) {
+    auto* q = static_cast<Payload*>(r->payload);
+    {
+      std::lock_guard<std::mutex> g(S->pin_mu);
+      S->pinned.give(q->pin_off, q->pin_bytes);
+    }
+    delete q;
     return pyjac::fail(PYJAC_E_INVALID, "server is shutting down");
   }
-  r->pin_off = off;
-  r->pin = S->pinned.ptr(off);
-  lk.unlock();
-  const size_t w = (size_t)n_states * 8;
-  std::memcpy(r->pin + P.phi, phi, (size_t)r->N * w);
-  std::memcpy(r->pin + P.p, p, w);
-  std::memcpy(r->pin + P.h, h, w);
-  std::memcpy(r->pin + P.rhs, rhs, (size_t)r->N * w);
-  lk.lock();
-  r->id = S->next_id++;
-  r->t_submit = t0;
-  S->pending.push_back(r);
-  S->all[r->id] = r;
-  *request_id = r->id;
-  lk.unlock();
-  S->cv_sched.notify_all();
+  *request_id = id;
   return PYJAC_OK;
 }
 
@@ -480,54 +529,75 @@ pyjac_status pyjac_serve_submit(pyjac_server* S, const pyjac_mech* mech, int64_t
 // unknown id / timeout.  A completed request is forgotten after this call.
 pyjac_status pyjac_serve_wait(pyjac_server* S, uint64_t request_id, double timeout_s, double* latency_s) {
   if (!S) return pyjac::fail(PYJAC_E_INVALID, "NULL server");
-  std::unique_lock<std::mutex> lk(S->mu);
-  auto it = S->all.find(request_id);
-  if (it == S->all.end()) return pyjac::fail(PYJAC_E_INVALID, "unknown request id");
-  auto r = it->second;
-  auto pred = [&] { return r->done; };
-  if (timeout_s < 0) S->cv_done.wait(lk, pred);
-  else if (!S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred))
-    return pyjac::fail(PYJAC_E_INVALID, "timed out");
+  std::shared_ptr<pyjac::sched::Request> r;
+  const int rc = S->sch->wait(request_id, timeout_s, &r);
+  if (rc < 0) return pyjac::fail(PYJAC_E_INVALID, "unknown request id");
+  if (rc == 0) return pyjac::fail(PYJAC_E_INVALID, "timed out");
   if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
-  S->all.erase(it);
-  if (r->status != PYJAC_OK) return pyjac::fail(r->status, S->error);
+  delete static_cast<Payload*>(r->payload);
+  r->payload = nullptr;
+  if (r->status != PYJAC_OK) {
+    std::lock_guard<std::mutex> g(S->err_mu);
+    return pyjac::fail(r->status, S->error);
+  }
   return PYJAC_OK;
 }
 
-// Totals since creation; p50/p99 latency over all completed requests.
+// Totals since creation; p50/p99 latency over all completed requests;
+// hbm_in_use: bytes of the resident pools.
 pyjac_status pyjac_serve_stats(pyjac_server* S, int64_t* requests_done, int64_t* states_done, int64_t* batches_done,
                                double* p50_s, double* p99_s, size_t* hbm_in_use) {
   if (!S) return pyjac::fail(PYJAC_E_INVALID, "NULL server");
-  std::lock_guard<std::mutex> g(S->mu);
-  if (requests_done) *requests_done = S->requests_done;
-  if (states_done) *states_done = S->states_done;
-  if (batches_done) *batches_done = S->batches_done;
-  std::vector<double> l = S->latencies;
+  pyjac::sched::Stats st = S->sch->stats();
+  if (requests_done) *requests_done = st.requests_done;
+  if (states_done) *states_done = st.states_done;
+  if (batches_done) *batches_done = st.rounds_done;
+  std::vector<double>& l = st.latencies;
   std::sort(l.begin(), l.end());
   auto pct = [&](double q) { return l.empty() ? 0.0 : l[std::min(l.size() - 1, (size_t)(q * (l.size() - 1) + 0.5))]; };
   if (p50_s) *p50_s = pct(0.50);
   if (p99_s) *p99_s = pct(0.99);
-  if (hbm_in_use) *hbm_in_use = S->arena.used();
+  if (hbm_in_use) {
+    std::lock_guard<std::mutex> g(S->reg_mu);
+    *hbm_in_use = S->pool_total;
+  }
   return PYJAC_OK;
 }
 
-// Finishes every submitted request, then releases the streams and the arena.
+pyjac_status pyjac_serve_graph_stats(pyjac_server* S, int64_t* eager_rounds, int64_t* captured_rounds,
+                                     int64_t* replayed_rounds, int64_t* jacobian_launches,
+                                     int64_t* multi_mechanism_launches) {
+  if (!S) return pyjac::fail(PYJAC_E_INVALID, "NULL server");
+  if (eager_rounds) *eager_rounds = S->n_eager;
+  if (captured_rounds) *captured_rounds = S->n_captured;
+  if (replayed_rounds) *replayed_rounds = S->n_replayed;
+  if (jacobian_launches) *jacobian_launches = S->n_jac_launches;
+  if (multi_mechanism_launches) *multi_mechanism_launches = S->n_multi_mech;
+  return PYJAC_OK;
+}
+
+// Finishes every submitted request, then releases graphs, pools and streams.
 pyjac_status pyjac_serve_destroy(pyjac_server* S) {
   if (!S) return PYJAC_OK;
+  S->sch->shutdown();
   {
-    std::lock_guard<std::mutex> g(S->mu);
-    S->stop = true;
+    std::lock_guard<std::mutex> g(S->pin_mu);
+    S->closing = true;
   }
-  S->cv_sched.notify_all();
-  S->cv_done.notify_all();
   S->cv_pin.notify_all();
-  if (S->sched.joinable()) S->sched.join();
-  if (S->reaper.joinable()) S->reaper.join();
   int prev = 0;
   hipGetDevice(&prev);
   hipSetDevice(S->device);
-  for (auto st : S->streams) { hipStreamSynchronize(st); hipStreamDestroy(st); }
+  for (auto st : S->streams) hipStreamSynchronize(st);
+  for (auto& gm : S->graphs)
+    for (auto& [sig, G] : gm)
+      if (G.exec) hipGraphExecDestroy(G.exec);
+  for (auto& pm : S->pools)
+    for (auto& [key, P] : pm) hipFree(P.mem);
+  for (auto ev : S->events) hipEventDestroy(ev);
+  for (auto st : S->streams) hipStreamDestroy(st);
   hipSetDevice(prev);
+  S->sch.reset();
   delete S;
   return PYJAC_OK;
 }

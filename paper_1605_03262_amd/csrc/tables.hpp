@@ -140,4 +140,22 @@ struct MechDev {
   const int* __restrict__ cv_colptr;       // [N + 1]
 };
 
+// One batch of a multi-mechanism work-list launch:
+// the mechanism's device view (with the species-list chunk bounds of the
+// launch shape), the batch's arrays and size, and its first tile in the grid.
+struct WorkItem {
+  MechDev md;
+  const double* phi;
+  const double* p;
+  double* jac;
+  int64_t n, ld, tile0;
+};
+// The work list travels as a kernel argument (no device copy, so a launch can
+// be captured into a graph as is): at most kMaxWorkItems batches per launch.
+constexpr int kMaxWorkItems = 8;
+struct WorkList {
+  WorkItem item[kMaxWorkItems];
+  int n_items;
+};
+
 }  // namespace pyjac

@@ -1,6 +1,7 @@
 """Continuous-batching server: every request's result equals the same request
 processed alone through the direct path (bitwise), also when requests of
-several mechanisms and sizes are packed together, under HBM backpressure."""
+several mechanisms and sizes share rounds, one Jacobian launch, and replayed
+HIP graphs; the work-list Jacobian launch itself equals per-mechanism launches."""
 import numpy as np
 import pytest
 
@@ -35,8 +36,7 @@ def test_results_same_alone_and_in_the_mix(mode):
         M = mechs[q % 3]
         n = int(rng.integers(1, 300))
         reqs.append((M,) + _request(rng, M.n_species, n))
-    # budget that cannot hold everything at once: forces backpressure
-    srv = Server(hbm_budget_bytes=256 << 20, max_batch_states=512, n_streams=3, max_refine=4,
+    srv = Server(hbm_budget_bytes=2 << 30, max_batch_states=512, n_streams=3, max_refine=4,
                  rtol=1e-14)
     ids = [srv.submit(M, phi, p, h, b, NEWTON_GAMMA, mode=mode) for (M, phi, p, h, b) in reqs]
     lat = [srv.wait(rid) for rid, _, _ in ids]
@@ -84,3 +84,59 @@ def test_close_without_waiting_finishes_every_request():
     for phi, p, h, b, x, info in outs:
         xa, ia = _alone(torch, M, phi, p, h, b, 0, 4, 1e-14)
         assert np.array_equal(info, ia) and np.array_equal(x, xa)
+
+
+def test_graph_replay_and_multi_mechanism_rounds():
+    """The same set of requests (three mechanisms) submitted round after round:
+    the first round of the sequence runs eagerly, the second is captured into a
+    graph, later ones replay it; mechanisms sharing a launch shape share one
+    Jacobian launch; every result equals the direct path bitwise."""
+    import torch
+    from paper_1605_03262_amd import Mechanism, Server
+    mechs = [Mechanism(text=config_mechanism(c).to_text()) for c in (0, 1, 2)]
+    srv = Server(hbm_budget_bytes=2 << 30, max_batch_states=512, n_streams=1, max_refine=4, rtol=1e-14)
+    rng = np.random.default_rng(23)
+    # per repetition: a 111-species request that keeps the single stream busy,
+    # then 13- and 53-species requests that queue meanwhile and share a round
+    sizes = {2: 500, 0: 100, 1: 50}
+    for rep in range(5):
+        batch = []
+        for c in (2, 0, 1):
+            M = mechs[c]
+            phi, p, h, b = _request(rng, M.n_species, sizes[c])
+            batch.append((M, phi, p, h, b) + srv.submit(M, phi, p, h, b, NEWTON_GAMMA, mode=0))
+        for M, phi, p, h, b, rid, x, info in batch:
+            srv.wait(rid)
+            xa, ia = _alone(torch, M, phi, p, h, b, 0, 4, 1e-14)
+            assert np.array_equal(info, ia) and np.array_equal(x, xa)
+    g = srv.graph_stats()
+    srv.close()
+    assert g["captured_rounds"] >= 1 and g["replayed_rounds"] >= 1, g
+    shapes = [tuple(M.get_variant(1)[:2]) for M in mechs]
+    if len(set(shapes)) < 3:
+        assert g["multi_mechanism_launches"] >= 1, (g, shapes)
+    print(f"graph stats {g}; shapes {shapes}")
+
+
+def test_work_list_launch_equals_single_launches():
+    import torch
+    from paper_1605_03262_amd import Mechanism, PyjacError, _lib
+    mechs = [Mechanism(text=config_mechanism(c).to_text()) for c in (0, 1)]
+    for M in mechs:
+        M.set_variant(1, 8, 512)
+    stream = torch.cuda.current_stream().cuda_stream
+    items, expect, outs = [], [], []
+    for k, (M, n) in enumerate(zip(mechs, (333, 517))):
+        phi, p = draw_states(40 + k, M.n_species, n)
+        d_phi, d_p = torch.from_numpy(phi).cuda(), torch.from_numpy(p).cuda()
+        out = torch.full((M.n_species ** 2, n), float("nan"), dtype=torch.float64, device="cuda")
+        items.append((M.handle, n, n, d_phi.data_ptr(), d_p.data_ptr(), out.data_ptr()))
+        outs.append((out, d_phi, d_p))
+        expect.append(M.eval_jacobian(d_phi, d_p))
+    _lib.pyjac_eval_jacobian_multi(items, stream)
+    torch.cuda.synchronize()
+    for (out, _, _), e in zip(outs, expect):
+        assert torch.equal(out, e)
+    mechs[1].set_variant(1, 4, 512)
+    with pytest.raises(PyjacError):
+        _lib.pyjac_eval_jacobian_multi(items, stream)
