@@ -33,6 +33,11 @@ HBM_PEAK_GBS = 8000.0
 CFG = 1
 
 
+def log(msg: str) -> None:
+    """Progress of the benchmark legs on stderr (the JSON line stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("kinetics.hip", "tables.hpp", "loader.cpp"):
@@ -206,28 +211,47 @@ def write_traffic(fetch_dir: str, write_dir: str) -> int:
     return 0
 
 
-def cpu_baseline(mech, phi, p, budget_s: float = 12.0):
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_leg(ref, phi, p, threads: int, budget_s: float):
+    """Oracle Jacobians on the first states of the batch for about budget_s."""
     import numpy as np
-    from oracle import RefMech
-    ref = RefMech(text=mech.to_text())
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
-    probe = 256
+    probe = 64 if threads == 1 else 256
     t0 = time.perf_counter()
     ref.eval_jacobian(phi[:, :probe], p[:probe], nthreads=threads)
     per_state = (time.perf_counter() - t0) / probe
     n = phi.shape[1]
-    reps = max(1, int(budget_s / max(per_state * n, 1e-9)))
     n_s = int(min(n, max(probe, budget_s / max(per_state, 1e-9))))
-    sub_phi, sub_p = np.ascontiguousarray(phi[:, :n_s]), p[:n_s]
+    sub_phi, sub_p = np.ascontiguousarray(phi[:, :n_s]), np.ascontiguousarray(p[:n_s])
     t0 = time.perf_counter()
-    for _ in range(reps if n_s == n else 1):
-        ref.eval_jacobian(sub_phi, sub_p, nthreads=threads)
+    ref.eval_jacobian(sub_phi, sub_p, nthreads=threads)
     dt = time.perf_counter() - t0
-    done = n_s * (reps if n_s == n else 1)
-    return {"value": done / dt, "unit": "Jacobian evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} Jacobians ({n_s} of the {n} states"
-                      f"{', x%d passes' % reps if n_s == n and reps > 1 else ''}), "
-                      f"{threads} OpenMP threads, {dt:.1f} s"}
+    return n_s / dt, n_s, dt
+
+
+def cpu_baseline(mech, phi, p, budget_s: float = 10.0):
+    """The oracle (plain C++, OpenMP over states, not tuned) on the host:
+    one thread and every available thread, each on the first states of the
+    benchmark batch for about budget_s seconds."""
+    from oracle import RefMech
+    ref = RefMech(text=mech.to_text())
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    v1, n1, t1 = _oracle_leg(ref, phi, p, 1, budget_s)
+    vn, nn, tn = _oracle_leg(ref, phi, p, threads, budget_s)
+    return {"value": vn, "unit": "Jacobian evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {nn} of the {phi.shape[1]} states, {threads} OpenMP threads, {tn:.1f} s; "
+                      f"single thread: first {n1} states, {t1:.1f} s",
+            "single_thread_value": v1, "cpu_model": _cpu_model()}
 
 
 def time_stream(fn, reps, torch):
@@ -243,6 +267,115 @@ def time_stream(fn, reps, torch):
     torch.cuda.synchronize()
     ms = np.array([a.elapsed_time(b) for a, b in ev])
     return float(np.median(ms)), float(ms.mean())
+
+
+R_GAS = 8314.462618      # J / (kmol K)
+
+
+def parity_sample(mech, phi, p, jac, x, h, rhs, gamma, n_sample=64, seed=3262 + 50):
+    """The timed step's own outputs on sampled states against the oracle:
+    E_norm of the Jacobian (the gate is 1e-10) and the relative error of the
+    Newton solution against a dense FP64 solve of (I - h gamma J_oracle) x = b
+    (LAPACK, partial pivoting), next to that system's condition number."""
+    import numpy as np
+    from oracle import RefMech
+    n, N = phi.shape[1], mech.n_species
+    idx = np.sort(np.random.default_rng(seed).choice(n, size=min(n_sample, n), replace=False))
+    import torch
+    sel = torch.from_numpy(idx).to(jac.device)
+    Jg = jac.index_select(1, sel).cpu().numpy()
+    xg = x.index_select(1, sel).cpu().numpy()
+    Jr = RefMech(text=mech.to_text()).eval_jacobian(np.ascontiguousarray(phi[:, idx]), p[idx])
+    scale = np.max(np.abs(Jr), axis=0)
+    scale[scale == 0] = 1.0
+    e = np.linalg.norm((Jg - Jr) / scale, axis=0) / np.linalg.norm(Jr / scale, axis=0)
+    xe, kap = [], []
+    for s, i in enumerate(idx):
+        A = np.eye(N) - h[i] * gamma * Jr[:, s].reshape(N, N)
+        xr = np.linalg.solve(A, rhs[:, i])
+        xe.append(np.linalg.norm(xg[:, s] - xr) / np.linalg.norm(xr))
+        kap.append(np.linalg.cond(A, np.inf))
+    return {"states": int(idx.size), "seed": seed, "jacobian_max_enorm": float(e.max()),
+            "jacobian_gate": 1e-10, "jacobian_pass": bool(e.max() <= 1e-10),
+            "newton_max_rel_err": float(max(xe)), "newton_max_cond_inf": float(max(kap))}
+
+
+def conc_states(mech, phi, p):
+    """(T, p, Y_1..Y_{N-1}) -> (T, [X_1..X_N]) by the ideal-gas law."""
+    import numpy as np
+    W = mech.molecular_weights()
+    Y = np.vstack([phi[1:], 1.0 - phi[1:].sum(axis=0)])
+    rho = p / (R_GAS * phi[0] * (Y / W[:, None]).sum(axis=0))
+    return np.ascontiguousarray(np.vstack([phi[:1], rho * Y / W[:, None]]))
+
+
+def conc_leg(M, mech, phi, p, torch, n_sample=32, seed=3262 + 51):
+    """Concentration-based, constant-volume Jacobian (sparse species block) on
+    the benchmark batch: autotuned launch shape, time per launch, algorithmic
+    bytes (state in, dense temperature row/column + u_k + the nnz values of S
+    out) and E_norm of sampled states against the oracle's dense Jacobian."""
+    import numpy as np
+    from oracle import RefMech
+    N, n = mech.n_species, phi.shape[1]
+    c = conc_states(mech, phi, p)
+    d_c = torch.from_numpy(c).cuda()
+    colptr, rowidx = M.conc_pattern()
+    nnz = len(rowidx)
+    rows = 3 * N + 1 + nnz
+    out = torch.empty((rows, n), dtype=torch.float64, device="cuda")
+    tuned = M.autotune(2, d_c, None, out=out, reps=3)
+    med, _ = time_stream(lambda: M.eval_jacobian_conc(d_c, out=out), 5, torch)
+    by = n * 8.0 * ((N + 1) + rows)
+    idx = np.sort(np.random.default_rng(seed).choice(n, size=min(n_sample, n), replace=False))
+    o = out.index_select(1, torch.from_numpy(idx).cuda()).cpu().numpy()
+    J = np.zeros((N + 1, N + 1, idx.size))
+    J[0, 0] = o[0]
+    J[1:, 0] = o[1:N + 1]
+    J[0, 1:] = o[N + 1:2 * N + 1]
+    J[1:, 1:] = o[2 * N + 1:3 * N + 1][:, None, :]
+    for j in range(N):
+        for q in range(colptr[j], colptr[j + 1]):
+            J[1 + rowidx[q], 1 + j] += o[3 * N + 1 + q]
+    Jg = J.reshape((N + 1) ** 2, idx.size)
+    Jr = RefMech(text=mech.to_text()).eval_jacobian_conc(np.ascontiguousarray(c[:, idx]))
+    scale = np.max(np.abs(Jr), axis=0)
+    scale[scale == 0] = 1.0
+    e = np.linalg.norm((Jg - Jr) / scale, axis=0) / np.linalg.norm(Jr / scale, axis=0)
+    ts, nt, lds = M.get_variant(2)
+    del out, d_c
+    return {"ms_per_launch": med, "evals_per_s": n / (med * 1e-3), "nnz_sparse_block": nnz,
+            "dense_entries": (N + 1) ** 2, "outputs_per_state": rows,
+            "algorithmic_bytes_per_state": by / n, "hbm_frac": by / (med * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "shape": {"tile_states": ts, "threads": nt, "lds_bytes": lds},
+            "autotune_ms": [{"tile_states": sh[0], "threads": sh[1], "ms": t} for sh, t in tuned],
+            "sample_max_enorm": float(e.max()), "sample_states": int(idx.size)}
+
+
+def cs_leg(M, d_phi, d_p, n_cs, jac_ms, n, torch):
+    """Complex-step Jacobian (the accuracy reference) on the first n_cs states."""
+    N = M.n_species
+    out = torch.empty((N * N, n_cs), dtype=torch.float64, device="cuda")
+    ph, pp = d_phi[:, :n_cs].contiguous(), d_p[:n_cs].contiguous()
+    M.eval_jacobian_cs(ph, pp, out=out)
+    med, _ = time_stream(lambda: M.eval_jacobian_cs(ph, pp, out=out), 3, torch)
+    per = med / n_cs
+    return {"states": n_cs, "ms_per_launch": med, "evals_per_s": n_cs / (med * 1e-3),
+            "cs_over_analytical_time_per_state": per / (jac_ms / n)}
+
+
+def rates_leg(M, d_phi, d_p, n, N, torch):
+    """Rates kernel: net production rates only, and every output (rop_f, rop_r,
+    pres_mod, wdot, dphi)."""
+    wd, _ = time_stream(lambda: M.eval_rates(d_phi, d_p, rop_f=False, rop_r=False, pres_mod=False,
+                                             wdot=True, dphi=True), 5, torch)
+    out = M.eval_rates(d_phi, d_p)
+    full, _ = time_stream(lambda: M.eval_rates(d_phi, d_p), 5, torch)
+    ts, nt, _ = M.get_variant(0)
+    n_out = sum(v.shape[0] for v in out.values())
+    return {"rhs_only_ms": wd, "rhs_evals_per_s": n / (wd * 1e-3),
+            "all_outputs_ms": full, "all_outputs_rows": n_out,
+            "all_outputs_hbm_frac": n * 8.0 * (N + 1 + n_out) / (full * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "shape": {"tile_states": ts, "threads": nt}}
 
 
 def serving_run(n_requests: int, seed: int = 7):
@@ -269,7 +402,7 @@ def serving_run(n_requests: int, seed: int = 7):
     total_states = sum(r[1].shape[1] for r in reqs)
 
     def run_server(gaps, mode):
-        srv = Server(hbm_budget_bytes=64 << 30, max_batch_states=8192, n_streams=4, max_refine=4)
+        srv = Server(hbm_budget_bytes=64 << 30, max_batch_states=4096, n_streams=4, max_refine=4)
         ids = []
         t0 = time.perf_counter()
         tnext = t0
@@ -282,13 +415,14 @@ def serving_run(n_requests: int, seed: int = 7):
         lat = [srv.wait(i) for i in ids]
         wall = time.perf_counter() - t0
         st = srv.stats()
+        st.update(srv.graph_stats())
         srv.close()
         return np.array(lat), wall, st
 
     served = {}
     gaps80 = None
     for mode, name in ((NEWTON_MIXED, "mixed_fp32_lu_fp64_refine"), (NEWTON_FP64, "fp64_lu")):
-        lat_b, wall_b, _ = run_server(np.zeros(n_requests), mode)     # closed burst: saturation
+        lat_b, wall_b, st_b = run_server(np.zeros(n_requests), mode)  # closed burst: saturation
         sat_rate = n_requests / wall_b
         loads = {}
         for frac in (0.5, 0.8, 0.95):
@@ -296,11 +430,16 @@ def serving_run(n_requests: int, seed: int = 7):
             if frac == 0.8 and gaps80 is None:
                 gaps80 = gaps
             lat, wall, st = run_server(gaps, mode)
+            log(f"serving {name} at {int(frac * 100)}% load done")
             loads[f"{int(frac * 100)}%"] = {
                 "arrival_rate_req_per_s": frac * sat_rate,
                 "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                "states_per_s": total_states / wall, "batches": st["batches"]}
+                "states_per_s": total_states / wall, "rounds": st["batches"],
+                "graph_replayed_rounds": st["replayed_rounds"]}
         served[name] = {"burst_saturation_req_per_s": sat_rate, "burst_states_per_s": total_states / wall_b,
+                        "burst_rounds": st_b["batches"],
+                        "burst_graphs": {k: st_b[k] for k in ("eager_rounds", "captured_rounds", "replayed_rounds",
+                                                              "jacobian_launches", "multi_mechanism_launches")},
                         "offered_load": loads}
 
     arrivals = np.cumsum(gaps80)
@@ -402,7 +541,7 @@ def main() -> int:
         M.eval_jacobian(d_phi, d_p, out=jac)
         if ev is not None:
             ev[1].record(stream)
-        newton(NEWTON_MIXED, d_h)
+        return newton(NEWTON_MIXED, d_h)
 
     for _ in range(args.warmup):
         step()
@@ -412,9 +551,16 @@ def main() -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(evs[k])
+        x_last, info_last = step(evs[k])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    log(f"timed {args.steps} steps: {elapsed * 1e3 / args.steps:.3f} ms/step")
+    # the last timed step's own outputs, checked against the oracle on sampled states
+    parity = parity_sample(mech, phi, p, jac, x_last, h_cond, rhs, NEWTON_GAMMA)
+    info_h = info_last[:n].cpu().numpy()
+    parity["newton_fp64_fallbacks"] = int((info_h == -2).sum())
+    parity["newton_singular"] = int((info_h == -1).sum())
+    del x_last, info_last
     jac_ms = np.array([a.elapsed_time(b) for a, b in evs])
     jac_avg_ms = float(jac_ms.mean())
     ms_per_step = elapsed * 1e3 / args.steps
@@ -424,6 +570,7 @@ def main() -> int:
     achieved = bytes_alg / (jac_avg_ms * 1e-3) / 1e9
     ts, nt, lds = M.get_variant(1)
 
+    log(f"parity sample: max E_norm {parity['jacobian_max_enorm']:.2e}, Newton rel err {parity['newton_max_rel_err']:.2e}")
     # the paper's comparison method: forward-difference Jacobian on the same batch
     fd_out = torch.empty_like(jac)
     fd_ws = torch.empty((_lib.pyjac_fd_workspace_bytes(M.handle, 16384),), dtype=torch.uint8, device="cuda")
@@ -437,6 +584,7 @@ def main() -> int:
                           "method": "first-order forward differences of the GPU RHS, chunks of 16384 states"}
     del fd_out, fd_ws
 
+    log("finite-difference Jacobian timed")
     # Newton alone, both modes, both step-size recipes
     newton_info = {}
     for label, hh in (("conditioned_h", d_h), ("configured_h", d_hcfg)):
@@ -452,7 +600,20 @@ def main() -> int:
                 sw = info[info > 0]
                 res[name]["refine_sweeps_mean"] = float(sw.mean()) if sw.size else None
         res["mixed_speedup"] = res["fp64_lu"]["ms_median"] / res["fp32_mfma_lu_fp64_refine"]["ms_median"]
+        # nominal LU flops (2/3 N^3) per state over the whole solve time (form, LU, solves, refinement)
+        for name in ("fp64_lu", "fp32_mfma_lu_fp64_refine"):
+            res[name]["lu_tflops_nominal"] = n * (2.0 / 3.0) * N ** 3 / (res[name]["ms_median"] * 1e-3) / 1e12
         newton_info[label] = res
+    newton_info["path"] = ("form A = I - h gamma J per state (LDS transpose), right-looking LU with 16-column "
+                           "panels, trailing update on 16x16x4 MFMA (FP32 in mixed mode, FP64 otherwise), "
+                           "triangular solves, FP64 residual refinement; non-converging states re-solved in FP64")
+    log("Newton timed")
+    rates_info = rates_leg(M, d_phi, d_p, n, N, torch)
+    log("rates timed")
+    conc_info = conc_leg(M, mech, phi, p, torch)
+    log("concentration-form Jacobian timed")
+    cs_info = cs_leg(M, d_phi, d_p, min(n, 8192), jac_med, n, torch)
+    log("complex-step Jacobian timed")
 
     out.update({
         "metric": "Jacobian evals/s (FP64, <=1e-10 rel err vs oracle) + p50/p99 request latency",
@@ -469,12 +630,17 @@ def main() -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic((ts, nt)),
                      "kernel": "tile_kernel (Jacobian)", "avg_launch_ms": jac_avg_ms,
                      "algorithmic_bytes_per_launch": bytes_alg},
+        "parity_sample": parity,
         "newton": newton_info,
+        "rates": rates_info,
+        "conc_jacobian": conc_info,
+        "complex_step_jacobian": cs_info,
         "fd_jacobian": fd_info,
     })
     if not args.no_serving:
         out["serving"] = serving_run(args.serving_requests)
     if not args.no_cpu_baseline:
+        log("CPU oracle legs")
         out["cpu_baseline"] = cpu_baseline(mech, phi, p)
     print(json.dumps(out), flush=True)
     return 0

@@ -10,7 +10,7 @@
 // completion thread polls in-flight rounds, lets the executor deliver their
 // results (without holding the lock), marks the requests done and records
 // their latencies.  The device side is the Executor: HIP streams, pools,
-// graphs and kernels in serve.cpp, a fake one in the CPU tests.
+// graphs and kernels in serve.hip, a fake one in the CPU tests.
 //
 // Lifetime rules that keep the two threads apart: a round enters `inflight`
 // only after the executor accepted it, and only the completion thread removes

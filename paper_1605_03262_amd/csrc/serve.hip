@@ -154,6 +154,7 @@ struct pyjac_server : public pyjac::sched::Executor {
   size_t budget = 0;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;
+  hipStream_t setup = nullptr;                         // pool fills, waited for at once
   PinnedArena pinned;
   std::mutex pin_mu;
   std::condition_variable cv_pin;
@@ -195,20 +196,33 @@ struct pyjac_server : public pyjac::sched::Executor {
 namespace {
 
 // Fills a new pool with valid states (T 1500 K, equal mass fractions, 1 atm,
-// h = 0 so that A = I), so that padding columns never hold garbage.
-pyjac_status init_pool(const pyjac_mech* m, Pool& P) {
+// h = 0 so that A = I, zero right-hand sides), so that padding columns never
+// hold garbage.  One thread per element of the N x C state block.
+__global__ void fill_pool_kernel(int N, int64_t C, double* __restrict__ phi, double* __restrict__ p,
+                                 double* __restrict__ h, double* __restrict__ rhs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (int64_t)N * C) {
+    phi[i] = i < C ? 1500.0 : 1.0 / N;
+    rhs[i] = 0.0;
+  }
+  if (i < C) {
+    p[i] = 101325.0;
+    h[i] = 0.0;
+  }
+}
+
+// The fill runs on the server's setup stream (not a round's stream, which may
+// be capturing a graph on the scheduler thread, and not the null stream), and
+// is waited for before the pool is registered.
+pyjac_status init_pool(const pyjac_mech* m, Pool& P, hipStream_t setup) {
   const int N = pyjac::mech_species(m);
-  const int64_t C = P.C;
-  std::vector<double> col((size_t)N * C);
-  for (int64_t s = 0; s < C; ++s) col[s] = 1500.0;
-  for (int k = 1; k < N; ++k)
-    for (int64_t s = 0; s < C; ++s) col[(size_t)k * C + s] = 1.0 / N;
-  std::vector<double> pv(C, 101325.0), zero((size_t)N * C, 0.0);
-  if (hipMemcpy(P.phi, col.data(), col.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(P.p, pv.data(), C * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(P.h, zero.data(), C * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(P.rhs, zero.data(), zero.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
-    return pyjac::fail(PYJAC_E_DEVICE, "pool initialization failed");
+  const int64_t total = (int64_t)N * P.C;
+  const int64_t blocks = (total + 255) / 256;
+  fill_pool_kernel<<<dim3((unsigned)blocks), dim3(256), 0, setup>>>(N, P.C, P.phi, P.p, P.h, P.rhs);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(setup);
+  if (e != hipSuccess)
+    return pyjac::fail(PYJAC_E_DEVICE, std::string("pool initialization failed: ") + hipGetErrorName(e));
   return PYJAC_OK;
 }
 
@@ -398,6 +412,10 @@ pyjac_status pyjac_serve_create(int32_t device, size_t hbm_budget_bytes, int64_t
     S->streams.push_back(st);
     S->events.push_back(ev);
   }
+  if (hipStreamCreateWithFlags(&S->setup, hipStreamNonBlocking) != hipSuccess) {
+    hipSetDevice(prev);
+    return pyjac::fail(PYJAC_E_DEVICE, "stream creation failed");
+  }
   S->pools.resize(n_streams);
   S->graphs.resize(n_streams);
   hipSetDevice(prev);
@@ -440,8 +458,10 @@ pyjac_status pyjac_serve_submit(pyjac_server* S, const pyjac_mech* mech, int64_t
         Pool P;
         P.C = C;
         P.bytes = pool_bytes(mech, C);
-        if (hipMalloc(&P.mem, P.bytes) != hipSuccess) {
-          rc = pyjac::fail(PYJAC_E_NOMEM, "pool allocation failed");
+        const hipError_t ea = hipMalloc(&P.mem, P.bytes);
+        if (ea != hipSuccess) {
+          P.mem = nullptr;
+          rc = pyjac::fail(PYJAC_E_NOMEM, std::string("pool allocation failed: ") + hipGetErrorName(ea));
           break;
         }
         char* b = static_cast<char*>(P.mem);
@@ -461,7 +481,7 @@ pyjac_status pyjac_serve_submit(pyjac_server* S, const pyjac_mech* mech, int64_t
         P.wsb = std::max(pyjac_newton_workspace_bytes(mech, C, 0), pyjac_newton_workspace_bytes(mech, C, 1));
         P.ws = take(P.wsb);
         made.push_back(P);
-        rc = init_pool(mech, made.back());
+        rc = init_pool(mech, made.back(), S->setup);
       }
       hipSetDevice(prev);
       if (rc != PYJAC_OK) {
@@ -596,6 +616,7 @@ pyjac_status pyjac_serve_destroy(pyjac_server* S) {
     for (auto& [key, P] : pm) hipFree(P.mem);
   for (auto ev : S->events) hipEventDestroy(ev);
   for (auto st : S->streams) hipStreamDestroy(st);
+  if (S->setup) hipStreamDestroy(S->setup);
   hipSetDevice(prev);
   S->sch.reset();
   delete S;
