@@ -260,6 +260,9 @@ __global__ void zero_int_kernel(int* p) { *p = 0; }
 //    states that do not converge within max_refine sweeps (or whose FP32
 //    factor is singular) are listed and re-solved by the FP64 kernel.
 constexpr int kSmallMax = 64;  // largest N taken by the register-resident path
+// register width of the path for N <= kSmallMax (launch_small instantiates
+// exactly these widths)
+constexpr int small_width(int N) { return N <= 16 ? 16 : N <= 32 ? 32 : N <= 48 ? 48 : N <= 56 ? 56 : 64; }
 constexpr int SW8 = 8;         // states (wavefronts) per workgroup
 constexpr int SRB = 16;        // Jacobian rows staged per LDS pass
 
@@ -465,6 +468,9 @@ __global__ __launch_bounds__(SW * 64, 2) void small_fp64_kernel(int N, int64_t n
   double* stage = xall + (size_t)SW * NM;                  // SRB * N * SW, then slack
   __shared__ int64_t sst[SW];                              // state of each wave, -1 if none
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  // a listed launch is sized for every state; workgroups past the listed
+  // count leave before any barrier
+  if (list && (int64_t)xcd_block() * SW >= *count) return;
   if (threadIdx.x < SW) {
     const int64_t lim = list ? *count : n;
     const int64_t slot = (int64_t)xcd_block() * SW + threadIdx.x;
@@ -601,6 +607,338 @@ __global__ void small_compact_kernel(int64_t n, const int* __restrict__ info, in
   if (info[s] == ST_UNSET || info[s] == ST_SING32) list[atomicAdd(count, 1)] = (int)s;
 }
 
+// ---------------------------------------------------------------- grouped FP32 factor
+// Mixed path for N <= 64 with S states per wavefront: a group of G = 64 / S
+// lanes holds one state, lane q of the group the rows q, q + G, ..., so each
+// lane keeps R = S rows of NC FP32 values in registers (R * G = 64 rows).
+// Halving the element width is what lets four states share a wavefront, and
+// every instruction of the elimination, the triangular solves and the
+// pivot search then serves S states at once.  Partial pivoting is implicit
+// (rows stay in place; each row records the step at which it was the pivot),
+// as in the FP64 register path.  The pivot key packs the magnitude (low six
+// mantissa bits cleared) with 63 - row, so one group maximum names the pivot
+// row, ties going to the lower row; the pivot row travels through LDS.  The
+// residual r = b - (I - h gamma J) x is formed in FP64 from the FP64 Jacobian
+// in memory at every sweep (the FP64 matrix does not fit beside the factor).
+constexpr int kGrpWaves = 4;   // wavefronts per workgroup
+constexpr int kGrpOcc = 2;     // wavefronts per SIMD the register budget is sized for
+constexpr int kGrpStage = 128; // staged Jacobian rows x states per workgroup
+
+template <int G>
+__device__ __forceinline__ unsigned group_max_u32(unsigned v) {
+  // quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  if constexpr (G >= 8) v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+  if constexpr (G >= 16) v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+  if constexpr (G >= 32) v = max(v, (unsigned)__shfl_xor((int)v, 16));
+  if constexpr (G >= 64) v = max(v, (unsigned)__shfl_xor((int)v, 32));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ double group_max_f64(double v) {
+  for (int o = 1; o < G; o <<= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+__device__ __forceinline__ void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+// Forward and back substitution with the grouped factor (FP32), right-hand
+// side b (the lane's rows, zero beyond N).  pv[K] is the pivot row of step K
+// and dinv[K] the reciprocal of its pivot (both per group, in LDS, read one
+// step ahead); the value of the pivot row reaches its group through
+// v_readlane, so no LDS round trip sits on the dependency chain.  The
+// solution lands in xo[0..N).
+template <int NC, int R, int S>
+__device__ __forceinline__ void grp_solve(float (&a)[R][NC], int (&stp)[R], float (&b)[R], int N, int g, int gl,
+                                          const int* pv, const float* dinv, float* xo) {
+  constexpr int G = 64 / S;
+  // the factor is loop-invariant across sweeps; keep the compiler from
+  // hoisting the masked multipliers of every step out of the sweep loop
+  sfor<0, R>([&](auto r) { opaque_regs<0, NC>(a[r]); });
+  opaque_regs<0, R>(stp);
+  // value of the pivot row's slot, broadcast from the pivot lane of each group
+  auto bcast = [&](int pr) -> float {
+    const int slot = pr / G, src = pr % G;
+    float v = b[0];
+    sfor<1, R>([&](auto r) { v = slot == r ? b[r] : v; });
+    float out = 0.0f;
+    sfor<0, S>([&](auto gg) {
+      const int lsrc = __builtin_amdgcn_readlane(src, gg * G) + gg * G;
+      const float w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lsrc));
+      out = g == gg ? w : out;
+    });
+    return out;
+  };
+  // every step runs (identity border up to NC), so the factor stays one set
+  // of registers
+  int pr_next = pv[0];
+  sfor<0, NC>([&](auto K) {
+    const int pr = pr_next;
+    if constexpr (K + 1 < NC) pr_next = pv[K + 1];
+    const float y = bcast(pr);
+    sfor<0, R>([&](auto r) { b[r] = fmaf(stp[r] > K ? -a[r][K] : 0.0f, y, b[r]); });
+    __builtin_amdgcn_sched_barrier(0);
+  });
+  pr_next = pv[NC - 1];
+  float di_next = dinv[NC - 1];
+  sfor<0, NC>([&](auto KK) {
+    constexpr int K = NC - 1 - decltype(KK)::value;
+    const int pr = pr_next;
+    const float di = di_next;
+    if constexpr (K > 0) {
+      pr_next = pv[K - 1];
+      di_next = dinv[K - 1];
+    }
+    const float xk = bcast(pr) * di;
+    if (gl == 0) xo[K] = xk;
+    sfor<0, R>([&](auto r) { b[r] = fmaf(stp[r] < K ? -a[r][K] : 0.0f, xk, b[r]); });
+    __builtin_amdgcn_sched_barrier(0);
+  });
+  wave_lds_sync();
+}
+
+// Jacobian rows [i0, i0 + rows) of the workgroup's WS states into LDS,
+// stage[((i - i0) * N + j) * WS + q] = J_ij of state q; runs of WS states
+// are contiguous in memory.  When the workgroup's states are all present
+// and the rows 16-byte aligned (`dma`), each lane moves two neighbouring
+// states of one element straight into LDS (global_load_lds, 16 bytes), so
+// that the whole chunk is in flight without occupying registers; otherwise
+// each thread serves one state (the block size is a multiple of WS) with 8
+// loads in flight through registers.
+template <int WS>
+__device__ __forceinline__ void grp_stage(int N, int64_t ld, const double* __restrict__ jac, const int64_t* sst,
+                                          bool dma, int i0, int rows, double* stage) {
+  constexpr int STRIDE = kGrpWaves * 64, UNR = 8;
+  static_assert(WS % 2 == 0, "pairs of states");
+  const int cnt = rows * N * WS;
+  if (dma) {
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const double* jb = jac + (int64_t)i0 * N * ld + sst[0];
+    for (int tb = wv * 128; tb < cnt; tb += kGrpWaves * 128) {
+      const int t = tb + 2 * lane;
+      if (t < cnt) __builtin_amdgcn_global_load_lds(jb + (int64_t)(t / WS) * ld + (t % WS), stage + tb, 16, 0, 0);
+    }
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    return;
+  }
+  const int64_t myst = sst[threadIdx.x % WS];
+  const double* jb = jac + (int64_t)i0 * N * ld + (myst >= 0 ? myst : 0);
+  for (int t0 = threadIdx.x; t0 < cnt; t0 += STRIDE * UNR) {
+    double v[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int t = t0 + u * STRIDE;
+      v[u] = (t < cnt && myst >= 0) ? jb[(int64_t)(t / WS) * ld] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int t = t0 + u * STRIDE;
+      if (t < cnt) stage[t] = v[u];
+    }
+  }
+}
+
+// Workgroup of kGrpWaves wavefronts, WS = kGrpWaves * S states.  info: sweep
+// count, ST_SING32 (zero or non-finite FP32 pivot column), ST_UNSET (no
+// convergence within max_refine sweeps) or -3 (non-finite input); the last
+// three are left for the FP64 fallback.  Dynamic LDS: the stage of SRB
+// Jacobian rows (grp_lds_bytes).
+template <int NC, int S>
+__global__ __launch_bounds__(kGrpWaves * 64, kGrpOcc) void grp_mixed_kernel(int N, int64_t n, int64_t ld,
+                                                                    const double* __restrict__ jac,
+                                                                    const double* __restrict__ h, double gamma,
+                                                                    const double* __restrict__ rhs,
+                                                                    double* __restrict__ x, int* __restrict__ info,
+                                                                    int max_refine, double rtol) {
+  constexpr int G = 64 / S, R = S, WS = kGrpWaves * S, SRB = kGrpStage / WS;
+  static_assert(NC % 4 == 0 && NC <= 64, "column count");
+  extern __shared__ double stage[];                        // SRB * N * WS
+  __shared__ __align__(16) float pbuf[kGrpWaves][S][NC];   // pivot row of the current step
+  __shared__ int pvbuf[kGrpWaves][S][64];                  // pivot row of each step
+  __shared__ float obuf[kGrpWaves][S][64];                 // FP32 solutions
+  __shared__ float dbuf[kGrpWaves][S][64];                 // pivot reciprocals
+  __shared__ __align__(16) double xbuf[kGrpWaves][S][64];  // FP64 solution
+  __shared__ int64_t sst[WS];                              // state of each group, -1 if none
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const int g = lane / G, gl = lane % G, q = wv * S + g;
+  if (threadIdx.x < WS) {
+    const int64_t slot = (int64_t)xcd_block() * WS + threadIdx.x;
+    sst[threadIdx.x] = slot < n ? slot : -1;
+  }
+  __syncthreads();
+  const int64_t s = sst[q];
+  const bool live = s >= 0;
+  const int64_t sc = live ? s : 0;
+  const double hg = live ? h[sc] * gamma : 0.0;
+  // all WS states present (consecutive), element rows 16-byte aligned
+  const bool dma = sst[WS - 1] >= 0 && (ld % 2) == 0 && ((uintptr_t)jac % 16) == 0;
+  float* pb = pbuf[wv][g];
+  int* pvb = pvbuf[wv][g];
+  float* ob = obuf[wv][g];
+  float* db = dbuf[wv][g];
+  double* xb = xbuf[wv][g];
+
+  // A = I - h gamma J in FP32, the lane's rows.  Rows and columns N..NC-1
+  // form an identity border (so every elimination step runs); rows >= NC
+  // are empty and count as already eliminated.
+  float a[R][NC];
+  bool used[R];
+  int stp[R];
+  bool fin = true;
+  sfor<0, R>([&](auto r) {
+    const int i = r * G + gl;
+    used[r] = !(live && i < NC);
+    stp[r] = used[r] ? 64 : -1;
+    sfor<0, NC>([&](auto j) { a[r][j] = (!used[r] && i >= N && i == j) ? 1.0f : 0.0f; });
+  });
+  for (int i0 = 0; i0 < N; i0 += SRB) {
+    const int rows = min(SRB, N - i0);
+    grp_stage<WS>(N, ld, jac, sst, dma, i0, rows, stage);
+    __syncthreads();
+    sfor<0, R>([&](auto r) {
+      const int i = r * G + gl;
+      if (!used[r] && i < N && i >= i0 && i < i0 + rows) {
+        const double* src = stage + (size_t)(i - i0) * N * WS + q;
+        sfor8<0, NC>([&](auto j) {
+          if (j < N) {
+            const double v = fma(-hg, src[j * WS], i == j ? 1.0 : 0.0);
+            fin = fin && isfinite(v);
+            a[r][j] = (float)v;
+          }
+        });
+      }
+    });
+    __syncthreads();
+  }
+  // a state is finite only if all its rows are
+  const bool gfin = group_max_u32<G>(fin ? 0u : 1u) == 0u;
+  bool bad = !gfin;
+
+  // elimination: every step runs (the identity border makes steps N..NC-1
+  // pick rows N..NC-1), so the factor stays one set of registers
+  sfor<0, NC>([&](auto K) {
+    {
+      unsigned best = 0u;
+      sfor<0, R>([&](auto r) {
+        const unsigned mag = (unsigned)__float_as_int(a[r][K]) & 0x7FFFFFFFu;
+        const unsigned key = used[r] ? 0u : ((mag & ~63u) | (unsigned)(63 - (r * G + gl)));
+        best = max(best, key);
+      });
+      const unsigned mk = group_max_u32<G>(best);
+      bad = bad || (mk >> 6) == 0u || (mk & ~63u) >= 0x7F800000u;
+      const int prow = 63 - (int)(mk & 63u);
+      constexpr int K4 = (decltype(K)::value) & ~3;
+      sfor<0, R>([&](auto r) {
+        if (!used[r] && r * G + gl == prow) {
+          used[r] = true;
+          stp[r] = K;
+          sfor<K4 / 4, NC / 4>([&](auto c4) {
+            *reinterpret_cast<float4*>(pb + 4 * c4) =
+                make_float4(a[r][4 * c4], a[r][4 * c4 + 1], a[r][4 * c4 + 2], a[r][4 * c4 + 3]);
+          });
+        }
+      });
+      wave_lds_sync();
+      const float rp = __builtin_amdgcn_rcpf(pb[K]);
+      if (gl == 0) {
+        db[K] = rp;
+        pvb[K] = prow;
+      }
+      float l[R];
+      sfor<0, R>([&](auto r) {
+        l[r] = used[r] ? 0.0f : a[r][K] * rp;
+        a[r][K] = used[r] ? a[r][K] : l[r];
+      });
+      sfor<K4 / 4, NC / 4>([&](auto c4) {
+        const float4 u = *reinterpret_cast<const float4*>(pb + 4 * c4);
+        const float uu[4] = {u.x, u.y, u.z, u.w};
+        sfor<0, 4>([&](auto c) {
+          constexpr int j = 4 * decltype(c4)::value + decltype(c)::value;
+          if constexpr (j > decltype(K)::value)
+            sfor<0, R>([&](auto r) { a[r][j] = fmaf(-l[r], uu[c], a[r][j]); });
+        });
+        __builtin_amdgcn_sched_barrier(0);
+      });
+      wave_lds_sync();
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  });
+  bad = bad || !live;
+
+  int status = gfin ? ST_UNSET : -3;
+  if (gfin && bad) status = live ? ST_SING32 : 0;
+  double bd[R];
+  sfor<0, R>([&](auto r) {
+    const int i = r * G + gl;
+    bd[r] = (live && i < N) ? rhs[(int64_t)i * ld + s] : 0.0;
+  });
+  // sweep 0: x = A32^-1 b; then FP64 residual, FP32 correction, until the
+  // correction is below rtol of the solution (max norms) or max_refine sweeps
+  {
+    float b[R];
+    sfor<0, R>([&](auto r) { b[r] = bad ? 0.0f : (float)bd[r]; });
+    grp_solve<NC, R, S>(a, stp, b, N, g, gl, pvb, db, ob);
+    if (!bad)
+      for (int k = gl; k < N; k += G) xb[k] = (double)ob[k];
+    wave_lds_sync();
+  }
+  bool done = bad;
+  for (int sweep = 1; sweep <= max_refine; ++sweep) {
+    if (!__syncthreads_or(!done)) break;          // uniform over the workgroup (it stages together)
+    float c[R];
+    sfor<0, R>([&](auto r) { c[r] = 0.0f; });
+    for (int i0 = 0; i0 < N; i0 += SRB) {
+      const int rows = min(SRB, N - i0);
+      grp_stage<WS>(N, ld, jac, sst, dma, i0, rows, stage);
+      __syncthreads();
+      sfor<0, R>([&](auto r) {
+        const int i = r * G + gl;
+        if (!done && i >= i0 && i < i0 + rows) {
+          const double* src = stage + (size_t)(i - i0) * N * WS + q;
+          double acc = 0.0;
+#pragma unroll 4
+          for (int j = 0; j < N; ++j) acc = fma(src[j * WS], xb[j], acc);
+          c[r] = (float)(bd[r] - (xb[i] - hg * acc));
+        }
+      });
+      __syncthreads();
+    }
+    grp_solve<NC, R, S>(a, stp, c, N, g, gl, pvb, db, ob);
+    double dm = 0.0, xm = 0.0;
+    bool xf = true;
+    if (!done)
+      for (int k = gl; k < N; k += G) {
+        const double d = (double)ob[k];
+        const double xn = xb[k] + d;
+        xb[k] = xn;
+        dm = fmax(dm, fabs(d));
+        xm = fmax(xm, fabs(xn));
+        xf = xf && isfinite(xn);
+      }
+    wave_lds_sync();
+    dm = group_max_f64<G>(dm);
+    xm = group_max_f64<G>(xm);
+    const bool gxf = group_max_u32<G>(xf ? 0u : 1u) == 0u;
+    if (!done && gxf && dm <= rtol * xm) {
+      status = sweep;
+      done = true;
+    }
+  }
+  if (live && gl == 0) info[s] = status;
+  if (live && status > 0)
+    sfor<0, R>([&](auto r) {
+      const int i = r * G + gl;
+      if (i < N) x[(int64_t)i * ld + s] = xb[i];
+    });
+}
+
+// stage of SRB Jacobian rows
+size_t grp_lds_bytes(int N, int S) {
+  const size_t WS = (size_t)kGrpWaves * S;
+  return (size_t)(kGrpStage / WS) * N * WS * sizeof(double);
+}
+
 // up to two SW x NM buffers + the stage + SW x NM slack for the masked
 // reads past the last staged row
 size_t small_lds(int N, int NM, int SW) { return ((size_t)SRB * N * SW + 3 * (size_t)SW * NM) * sizeof(double); }
@@ -627,13 +965,20 @@ hipError_t launch_small_t(int N, int64_t n, int64_t ld, const double* jac, const
                        (const int*)nullptr, (const int*)nullptr, fstore, sstore, fstat, fws ? fmode : 0);
     return hipGetLastError();
   }
-  constexpr int SWM = SW8;
-  const size_t ldsm = small_lds(N, NM, SWM);
-  auto km = small_mixed_kernel<NM>;
-  e = hipFuncSetAttribute((const void*)km, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsm);
+  // mixed: grouped FP32 factor, S states per wavefront (4 up to 16 columns,
+  // 2 above: S * NC FP32 values per lane stay within the register budget of
+  // two wavefronts per SIMD without spills)
+  // (the 32-column instance spills at two states per wavefront, so those
+  // sizes take the 48-column one)
+  constexpr int NC = NM == 32 ? 48 : NM;
+  constexpr int S = NC <= 16 ? 4 : 2;
+  constexpr int per_block = kGrpWaves * S;
+  const size_t glds = grp_lds_bytes(N, S);
+  auto kg = grp_mixed_kernel<NC, S>;
+  e = hipFuncSetAttribute((const void*)kg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(km, dim3((unsigned)((n + SWM - 1) / SWM)), dim3(SWM * 64), ldsm, st, N, n, ld, jac, h, gamma,
-                     rhs, x, info, max_refine, rtol);
+  hipLaunchKernelGGL(kg, dim3((unsigned)((n + per_block - 1) / per_block)), dim3(kGrpWaves * 64), glds, st, N, n,
+                     ld, jac, h, gamma, rhs, x, info, max_refine, rtol);
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, count);
   hipLaunchKernelGGL(small_compact_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
                      (const int*)info, list, count);
@@ -645,15 +990,13 @@ hipError_t launch_small_t(int N, int64_t n, int64_t ld, const double* jac, const
 hipError_t launch_small(int N, int64_t n, int64_t ld, const double* jac, const double* h, double gamma,
                         const double* rhs, double* x, int* info, int mode, int max_refine, double rtol,
                         int* list, int* count, hipStream_t st, void* fws, int fmode) {
-  // register width: N rounded up to a multiple of 8 (the work per state
-  // grows as NM^2, so the identity border is kept narrow)
+  // register width: N rounded up to 16, 32, 48, 56 or 64 (the work per
+  // state grows as NM^2, so the identity border is kept narrow where the
+  // workloads sit; fewer widths keep the build short)
 #define PYJAC_SMALL(nm) \
-  if (N <= nm) return launch_small_t<nm>(N, n, ld, jac, h, gamma, rhs, x, info, mode, max_refine, rtol, list, count, st, fws, fmode);
-  PYJAC_SMALL(8)
+  if (small_width(N) == nm) return launch_small_t<nm>(N, n, ld, jac, h, gamma, rhs, x, info, mode, max_refine, rtol, list, count, st, fws, fmode);
   PYJAC_SMALL(16)
-  PYJAC_SMALL(24)
   PYJAC_SMALL(32)
-  PYJAC_SMALL(40)
   PYJAC_SMALL(48)
   PYJAC_SMALL(56)
   PYJAC_SMALL(64)
@@ -826,7 +1169,7 @@ size_t small_ws_bytes(int64_t n, int mode) { return mode == 1 ? align256((size_t
 // FP64 factor kept for reuse on the register path (mode 0): rows of NM
 // doubles, NM pivot steps and one status per state
 size_t small_keep_bytes(int N, int64_t n) {
-  const size_t NM = (size_t)((N + 7) / 8) * 8;
+  const size_t NM = (size_t)small_width(N);
   return align256((size_t)n * NM * NM * sizeof(double)) + align256((size_t)n * NM * sizeof(int)) +
          align256((size_t)n * sizeof(int));
 }
