@@ -16,6 +16,8 @@
 //              straight from the state-fastest Jacobian (coalesced).
 // Mode 1 (mixed) factors in FP32, refines in FP64 and re-solves the states
 // that do not converge with the FP64 path (compacted list, device-side).
+// Systems with N <= 64 take register-resident kernels instead (FP64: one
+// state per wavefront; FP32 factor: several states per wavefront).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -243,10 +245,11 @@ __global__ __launch_bounds__(LU_THREADS) void lu_kernel(int N, int64_t n, T* __r
 __global__ void zero_int_kernel(int* p) { *p = 0; }
 
 // ---------------------------------------------------------------- small systems
-// N <= 64: one wavefront per state, lane i holding row i of I - h gamma J in
-// registers (NM = N rounded up to a multiple of 8 columns, indexed by
-// compile-time constants only; columns N..NM-1 are zero, so every update runs
-// unguarded over the full width).  A block of SW states shares one workgroup only to read the
+// N <= 64, FP64 (mode 0, and the mixed mode's fallback): one wavefront per
+// state, lane i holding row i of I - h gamma J in registers (NM = N rounded
+// up to 16, 32, 48, 56 or 64 columns, indexed by compile-time constants
+// only; the border is an identity, so every update runs unguarded over the
+// full width).  A block of SW states shares one workgroup only to read the
 // state-fastest Jacobian in coalesced 64-byte runs through LDS; after that
 // every wavefront factors and solves on its own, with no barrier:
 //  * right-looking LU with partial pivoting, rows kept in place (lane i keeps
@@ -255,10 +258,9 @@ __global__ void zero_int_kernel(int* p) { *p = 0; }
 //    the high 32 bits of the FP64/FP32 pattern, which order non-negative
 //    values; ties go to the lowest lane); the pivot row reaches the other
 //    lanes through v_readlane.
-//  * forward and backward substitution in pivot order, in the factor's precision.
-//  * mixed mode: FP32 factor, FP64 rows kept beside it for the residuals;
-//    states that do not converge within max_refine sweeps (or whose FP32
-//    factor is singular) are listed and re-solved by the FP64 kernel.
+//  * forward and backward substitution in pivot order.
+// The mixed mode's FP32 factor has its own kernel (grp_mixed_kernel, below);
+// states it leaves unconverged or singular are listed and re-solved here.
 constexpr int kSmallMax = 64;  // largest N taken by the register-resident path
 // register width of the path for N <= kSmallMax (launch_small instantiates
 // exactly these widths)
@@ -525,78 +527,6 @@ __global__ __launch_bounds__(SW * 64, 2) void small_fp64_kernel(int N, int64_t n
   }
   if (live && lane == 0) info[s] = status;
   if (solved && lane < N) x[(int64_t)lane * ld + s] = xv[lane];
-}
-
-// Mixed path: FP32 factor, FP64 residuals from the FP64 rows, at most
-// max_refine sweeps; status ST_UNSET (not converged) or ST_SING32 (FP32 factor
-// singular) is left in info for the FP64 fallback.
-template <int NM, int SW = SW8>
-__global__ __launch_bounds__(SW * 64, 2) void small_mixed_kernel(int N, int64_t n, int64_t ld,
-                                                                 const double* __restrict__ jac,
-                                                                 const double* __restrict__ h, double gamma,
-                                                                 const double* __restrict__ rhs,
-                                                                 double* __restrict__ x, int* __restrict__ info,
-                                                                 int max_refine, double rtol) {
-  extern __shared__ double slds[];
-  double* xall = slds;                                     // SW * NM
-  double* dall = xall + (size_t)SW * NM;                   // SW * NM
-  double* stage = dall + (size_t)SW * NM;                  // SRB * N * SW
-  __shared__ int64_t sst[SW];                              // state of each wave, -1 if none
-  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
-  if (threadIdx.x < SW) {
-    const int64_t slot = (int64_t)xcd_block() * SW + threadIdx.x;
-    sst[threadIdx.x] = slot < n ? slot : -1;
-  }
-  __syncthreads();
-  const int64_t s = sst[wv];
-  const bool live = s >= 0;
-  double* xv = xall + (size_t)wv * NM;
-  double* dv = dall + (size_t)wv * NM;
-  if (lane < NM) {
-    xv[lane] = 0.0;
-    dv[lane] = 0.0;
-  }
-  const double hg = live ? h[s] * gamma : 0.0;
-  double a64[NM];
-  const bool fin = __all(small_load<NM, SW>(a64, N, ld, jac, sst, hg, lane, wv, stage));
-  const double b = (live && lane < N) ? rhs[(int64_t)lane * ld + s] : 0.0;
-  int status = fin ? ST_UNSET : -3;
-  if (live && fin) {
-    float a32[NM];
-    sfor<0, NM>([&](auto j) { a32[j] = (float)a64[j]; });
-    int stp;
-    if (!small_lu<NM, float>(a32, lane, stp)) {
-      status = ST_SING32;
-    } else {
-      small_solve<NM, float>(a32, stp, b, xv);                     // sweep 0
-      for (int sweep = 1; sweep <= max_refine; ++sweep) {
-        opaque_regs<0, NM>(a32);
-        double r = b;                                                 // r = b - A x, FP64
-        sfor8<0, NM>([&](auto j) { r -= a64[j] * xv[j]; });
-        small_solve<NM, float>(a32, stp, r, dv);
-        double dm = 0.0, xm = 0.0;
-        bool xf = true;
-        if (lane < N) {
-          const double xn = xv[lane] + dv[lane];
-          xv[lane] = xn;
-          dm = fabs(dv[lane]);
-          xm = fabs(xn);
-          xf = isfinite(xn);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        for (int o = 32; o > 0; o >>= 1) {
-          dm = fmax(dm, __shfl_xor(dm, o));
-          xm = fmax(xm, __shfl_xor(xm, o));
-        }
-        if (__all(xf) && dm <= rtol * xm) {
-          status = sweep;
-          break;
-        }
-      }
-    }
-  }
-  if (live && lane == 0) info[s] = status;
-  if (live && status > 0 && lane < N) x[(int64_t)lane * ld + s] = xv[lane];
 }
 
 // States whose mixed solve left ST_UNSET or ST_SING32 go to the fallback list.
