@@ -530,8 +530,8 @@ pyjac_status pyjac_mech_set_variant(pyjac_mech* m, int32_t which, int32_t ts, in
     if (ts <= 0 || nt <= 0 || nt % ts) return fail(PYJAC_E_INVALID, "bad variant");
     if (kpt_of(m->host.N, ts, nt) > 8 || tile_lds_bytes(m->host.N, m->host.NR, m->host.NG, ts, nt, jac) > m->max_lds)
       return fail(PYJAC_E_UNSUPPORTED, "variant does not fit");
-    static const int ok[][2] = {{16, 512}, {16, 1024}, {8, 512}, {8, 1024}, {4, 512},
-                                {4, 1024}, {2, 512},  {2, 1024}, {32, 1024}, {64, 1024}};
+    static const int ok[][2] = {{16, 512}, {16, 1024}, {8, 512}, {8, 1024}, {4, 512}, {4, 1024},
+                                {2, 512},  {2, 1024}, {32, 1024}, {64, 1024}, {8, 256}, {4, 256}};
     bool found = false;
     for (auto& q : ok) found |= (q[0] == ts && q[1] == nt);
     if (!found) return fail(PYJAC_E_UNSUPPORTED, "variant not compiled");
@@ -554,8 +554,8 @@ pyjac_status pyjac_mech_autotune(pyjac_mech* m, int32_t which, int64_t n, int64_
   if (n_entries) *n_entries = 0;
   const bool jac = which == 1;
   const hipStream_t st = static_cast<hipStream_t>(stream);
-  static const int shapes_all[][2] = {{16, 1024}, {16, 512}, {32, 1024}, {64, 1024}, {8, 512},
-                                      {8, 1024},  {4, 512},  {4, 1024},  {2, 512},   {2, 1024}};
+  static const int shapes_all[][2] = {{16, 1024}, {16, 512}, {32, 1024}, {64, 1024}, {8, 512}, {8, 1024},
+                                      {4, 512},   {4, 1024}, {2, 512},   {2, 1024},  {8, 256}, {4, 256}};
   int prev = 0;
   hipGetDevice(&prev);
   hipSetDevice(m->device);

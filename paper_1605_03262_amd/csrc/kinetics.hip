@@ -749,8 +749,14 @@ __device__ __forceinline__ void tile_body(const MechDev& md, unsigned tile, int6
   }
 }
 
+// Register budget of the tile kernels, as wavefronts per SIMD: 4 (128
+// registers) for 512- and 1024-thread workgroups; 3 (168 registers, no
+// spills at 53 species) for 256-thread ones, whose LDS lets three
+// workgroups share a CU.
+constexpr int tile_waves_per_eu(int nt) { return nt == 256 ? 3 : (nt <= 512 ? 4 : 1); }
+
 template <int TS, int NT, int KPT, bool JAC, bool SPLIT>
-__global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev md, int64_t n, int64_t ld,
+__global__ __launch_bounds__(NT, tile_waves_per_eu(NT)) void tile_kernel(MechDev md, int64_t n, int64_t ld,
                                                   const double* __restrict__ phi,
                                                   const double* __restrict__ pin,
                                                   double* __restrict__ rop_f, double* __restrict__ rop_r,
@@ -766,7 +772,7 @@ __global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_kernel(MechDev m
 // form and an upper bound KPT of species per thread; the dynamic LDS is the
 // largest item's).  Per state the results are those of tile_kernel.
 template <int TS, int NT, int KPT, bool SPLIT>
-__global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void tile_multi_kernel(WorkList wl) {
+__global__ __launch_bounds__(NT, tile_waves_per_eu(NT)) void tile_multi_kernel(WorkList wl) {
   const unsigned t = xcd_tile();
   int i = 0;
   while (i + 1 < wl.n_items && (int64_t)t >= wl.item[i + 1].tile0) ++i;
@@ -807,7 +813,7 @@ struct CvLayout {
 };
 
 template <int TS, int NT, int KPT>
-__global__ __launch_bounds__(NT, (NT <= 512 ? 4 : 1)) void conc_tile_kernel(MechDev md, int64_t n, int64_t ld,
+__global__ __launch_bounds__(NT, tile_waves_per_eu(NT)) void conc_tile_kernel(MechDev md, int64_t n, int64_t ld,
                                                                            const double* __restrict__ phi,
                                                                            double* __restrict__ out) {
   constexpr int Gr = NT / TS;
@@ -1167,6 +1173,8 @@ hipError_t launch_tile_multi(int TS, int NT, int kpt, bool split, const WorkList
     return hipErrorInvalidValue; \
   }
   PYJAC_MULTI(16, 1024)
+  PYJAC_MULTI(8, 256)
+  PYJAC_MULTI(4, 256)
   PYJAC_MULTI(8, 512)
   PYJAC_MULTI(8, 1024)
   PYJAC_MULTI(4, 512)
@@ -1212,6 +1220,8 @@ hipError_t launch_tile(bool jac_mode, int TS, int NT, const MechDev& md, int64_t
                         : launch_k<ts, nt, true, false>(kpt, md, n, ld, phi, p, rop_f, rop_r, pmod, wdot, dphi, jac, lds, st);
   PYJAC_VARIANT(16, 1024)
   PYJAC_VARIANT(16, 512)
+  PYJAC_VARIANT(8, 256)
+  PYJAC_VARIANT(4, 256)
   PYJAC_VARIANT(32, 1024)
   PYJAC_VARIANT(64, 1024)
   PYJAC_VARIANT(8, 512)

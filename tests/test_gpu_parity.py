@@ -151,7 +151,7 @@ def test_split_form_parity_and_shapes(torch, Ref, seed, last):
     base = gpu_jac(torch, M, phi, p, ld=157)
     check_jac(base, ref.eval_jacobian(phi, p), "split")
     tried = 0
-    for ts, nt in ((16, 1024), (8, 512), (4, 1024), (2, 512)):
+    for ts, nt in ((16, 1024), (8, 512), (4, 1024), (2, 512), (8, 256), (4, 256)):
         try:
             M.set_variant(1, ts, nt)
         except Exception:
@@ -228,7 +228,7 @@ def test_launch_shape_does_not_change_results(torch):
     base_j = gpu_jac(torch, M, phi, p)
     base_r = gpu_rates(torch, M, phi, p)
     tried = 0
-    for ts, nt in ((8, 512), (8, 1024), (4, 512), (16, 1024), (4, 1024)):
+    for ts, nt in ((8, 512), (8, 1024), (4, 512), (16, 1024), (4, 1024), (8, 256), (4, 256)):
         try:
             M.set_variant(1, ts, nt)
             M.set_variant(0, ts, nt)
