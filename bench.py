@@ -652,7 +652,11 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic((ts, nt)),
                      "kernel": "tile_kernel (Jacobian)", "avg_launch_ms": jac_avg_ms,
-                     "algorithmic_bytes_per_launch": bytes_alg},
+                     "algorithmic_bytes_per_launch": bytes_alg,
+                     "traffic_source": "profiles/jacobian_c1_100k_traffic.json: rocprofv3 --pmc FETCH_SIZE and "
+                                       "WRITE_SIZE runs of bench.py --pmc-pass, copy-calibrated; null unless the "
+                                       "kernel source hash and launch shape match this run",
+                     "target_frac": 0.60},
         "parity_sample": parity,
         "newton": newton_info,
         "rates": rates_info,
