@@ -2,9 +2,11 @@
 // the comparison method of the paper's performance study (Sec. 5), built on
 // the library's own RHS kernel.
 //
-// For a chunk of m states, the perturbation kernel writes m*(N+1) states:
-// state s occupies columns c = s*(N+1) + 0 (unperturbed) and s*(N+1) + 1 + j
-// (Phi_j raised by its increment).  The RHS kernel evaluates them all; the
+// For a chunk of m states, the perturbation kernel writes m*(N+1) states in
+// N+1 blocks of m columns: block 0 holds the unperturbed states and block
+// 1 + j the states with Phi_j raised by its increment, state s at column
+// block*m + s, so that every kernel reads and writes consecutive states with
+// consecutive lanes.  The RHS kernel evaluates them all; the
 // difference kernel forms J_ij = (f_i(Phi + d_j e_j) - f_i(Phi)) / d_j, where
 // d_j is the increment actually represented, (Phi_j + inc_j) - Phi_j, with
 // inc_j = sqrt(u) * max(|Phi_j|, floor_j) (floor 1 K for the temperature,
@@ -29,7 +31,7 @@ __global__ __launch_bounds__(64) void fd_perturb_kernel(int N, int64_t m, int64_
   const int c = blockIdx.y;               // 0: base, 1 + j: Phi_j perturbed
   if (sl >= m) return;
   const int64_t s = s0 + sl;
-  const int64_t col = sl * (N + 1) + c;
+  const int64_t col = (int64_t)c * m + sl;
   for (int k = 0; k < N; ++k) {
     double v = phi[(int64_t)k * ld + s];
     if (c == k + 1) {
@@ -50,10 +52,10 @@ __global__ __launch_bounds__(64) void fd_diff_kernel(int N, int64_t m, const dou
   const int64_t sl = (int64_t)blockIdx.x * 64 + threadIdx.x;
   const int i = blockIdx.y;
   if (sl >= m) return;
-  const double* fr = f2 + (int64_t)i * ld2 + sl * (N + 1);
+  const double* fr = f2 + (int64_t)i * ld2 + sl;
   const double f0 = fr[0];
   for (int j = 0; j < N; ++j)
-    jac[((int64_t)i * N + j) * ld + s0 + sl] = (fr[1 + j] - f0) / inc[(int64_t)j * m + sl];
+    jac[((int64_t)i * N + j) * ld + s0 + sl] = (fr[(int64_t)(1 + j) * m] - f0) / inc[(int64_t)j * m + sl];
 }
 
 }  // namespace
