@@ -389,6 +389,46 @@ def rates_leg(M, d_phi, d_p, n, N, torch):
             "shape": {"tile_states": ts, "threads": nt}}
 
 
+def pasr_leg(mech, M, torch, n_reactors=100, n_res=0.2, seed=3262 + 52):
+    """PaSR particle driver (App. C) on the benchmark mechanism: 100 reactors
+    of 100 particles, T_in 600 K, 10 atm, tau_res 5 ms, tau_mix = tau_pair
+    = 1 ms, advanced n_res residence times; then the Jacobian timed on the
+    resulting particle states (the paper's own test distribution), with the
+    E_norm of 32 sampled states against the oracle."""
+    import numpy as np
+    from oracle import RefMech
+    from paper_1605_03262_amd.pasr import PaSR, burn
+    from synth import ATM, pasr_fresh
+    p_pa = 10 * ATM
+    fresh = pasr_fresh(mech, 600.0, seed)
+    hot = fresh.copy()
+    hot[0] = 2000.0
+    pilot = burn(M, hot, p_pa)
+    reactor = PaSR(M, n_reactors=n_reactors, fresh=fresh, pilot=pilot, p_pa=p_pa, tau_res=5e-3, seed=seed)
+    t0 = time.perf_counter()
+    phi, p = reactor.run(n_res)
+    wall = time.perf_counter() - t0
+    n = phi.shape[1]
+    steps = max(1, round(n_res * reactor.tau_res / reactor.dt))
+    d_phi, d_p = torch.from_numpy(phi).cuda(), torch.from_numpy(p).cuda()
+    N = mech.n_species
+    jac = torch.empty((N * N, n), dtype=torch.float64, device="cuda")
+    M.eval_jacobian(d_phi, d_p, out=jac)
+    med, _ = time_stream(lambda: M.eval_jacobian(d_phi, d_p, out=jac), 5, torch)
+    idx = np.sort(np.random.default_rng(seed).choice(n, size=32, replace=False))
+    Jg = jac.index_select(1, torch.from_numpy(idx).cuda()).cpu().numpy()
+    Jr = RefMech(text=mech.to_text()).eval_jacobian(np.ascontiguousarray(phi[:, idx]), p[idx])
+    scale = np.max(np.abs(Jr), axis=0)
+    scale[scale == 0] = 1.0
+    e = np.linalg.norm((Jg - Jr) / scale, axis=0) / np.linalg.norm(Jr / scale, axis=0)
+    return {"particles": n, "reactors": n_reactors, "time_steps": steps, "sub_steps_per_step": reactor.n_sub,
+            "wall_s": wall, "particle_steps_per_s": n * steps / wall,
+            "frozen_particle_steps": int(getattr(reactor, "frozen", 0)),
+            "T_range_K": [float(phi[0].min()), float(phi[0].max())],
+            "jacobian_ms_on_pasr_states": med, "jacobian_evals_per_s_on_pasr_states": n / (med * 1e-3),
+            "sample_max_enorm": float(e.max())}
+
+
 def serving_run(n_requests: int, seed: int = 7):
     """Poisson streams of Jacobian + mixed-Newton requests over the 13/53/111/
     360-species mechanisms (weights 0.4/0.3/0.2/0.1), n = floor(exp(U[0, ln 4097)))
@@ -637,6 +677,8 @@ def main() -> int:
     log("concentration-form Jacobian timed")
     cs_info = cs_leg(M, d_phi, d_p, min(n, 8192), jac_med, n, torch)
     log("complex-step Jacobian timed")
+    pasr_info = pasr_leg(mech, M, torch)
+    log("PaSR driver and Jacobian on its states timed")
 
     out.update({
         "metric": "Jacobian evals/s (FP64, <=1e-10 rel err vs oracle) + p50/p99 request latency",
@@ -662,6 +704,7 @@ def main() -> int:
         "rates": rates_info,
         "conc_jacobian": conc_info,
         "complex_step_jacobian": cs_info,
+        "pasr": pasr_info,
         "fd_jacobian": fd_info,
     })
     if not args.no_serving:

@@ -32,9 +32,13 @@ from . import NEWTON_FP64, Mechanism, _lib, _torch
 class PaSR:
     def __init__(self, mech: Mechanism, n_reactors: int, fresh, pilot, p_pa: float, n_part: int = 100,
                  tau_res: float = 5e-3, tau_mix: float = 1e-3, tau_pair: float = 1e-3, react_steps: int = 4,
-                 newton_iters: int = 6, seed: int = 0):
+                 newton_iters: int = 10, seed: int = 0):
         """fresh, pilot: (T, Y_1..Y_{N-1}) compositions of the inflow streams
-        (numpy, length N); p_pa: the reactor pressure."""
+        (numpy, length N); p_pa: the reactor pressure.  newton_iters: the
+        simplified-Newton iterations of each SDIRK3 stage (with 6, the
+        acceptance test below rejected most full sub-steps of burning
+        particles and their steps shrank to the floor; with 10 most particles
+        take a sub-step in one implicit step)."""
         if n_part % 2:
             raise ValueError("n_part must be even")
         torch = _torch()
