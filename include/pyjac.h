@@ -265,10 +265,14 @@ size_t pyjac_newton_workspace_bytes(const pyjac_mech* mech, int64_t n_states, in
  *   rhs    [N][ld]   right-hand side b
  *   x      [N][ld]   solution (may not alias rhs or jac)
  *   mode 0: LU with partial pivoting in FP64.
- *   mode 1: LU with partial pivoting in FP32 on the matrix cores, FP64
- *           residual r = b - A x and up to max_refine refinement sweeps until
- *           ||dx||_inf <= rtol * ||x||_inf; a state that does not converge is
- *           re-solved in FP64 (counted in info).
+ *   mode 1: LU with partial pivoting in FP32 (on the matrix cores for
+ *           N > 64; for N <= 64 in registers, several states per wavefront),
+ *           FP64 residual r = b - A x and up to max_refine refinement sweeps,
+ *           until ||dx||_inf <= rtol * ||x||_inf, or, from the second sweep,
+ *           until the contraction rho = ||dx_k|| / ||dx_k-1|| < 1/2 predicts
+ *           the remaining error rho / (1 - rho) ||dx_k||_inf <= rtol *
+ *           ||x||_inf; a state that does not converge is re-solved in FP64
+ *           (counted in info).
  *   info   [ld]      >= 0: refinement sweeps used (mode 1; 0 for mode 0);
  *                    -1: zero pivot (singular A); -2: mode-1 state fell back to
  *                    FP64 and converged there; -3: non-finite input.

@@ -814,6 +814,7 @@ __global__ __launch_bounds__(kGrpWaves * 64, kGrpOcc) void grp_mixed_kernel(int 
     wave_lds_sync();
   }
   bool done = bad;
+  double dprev = 0.0;                             // the previous sweep's correction (max norm)
   for (int sweep = 1; sweep <= max_refine; ++sweep) {
     if (!__syncthreads_or(!done)) break;          // uniform over the workgroup (it stages together)
     float c[R];
@@ -850,10 +851,16 @@ __global__ __launch_bounds__(kGrpWaves * 64, kGrpOcc) void grp_mixed_kernel(int 
     dm = group_max_f64<G>(dm);
     xm = group_max_f64<G>(xm);
     const bool gxf = group_max_u32<G>(xf ? 0u : 1u) == 0u;
-    if (!done && gxf && dm <= rtol * xm) {
+    // converged when the correction is below rtol of the solution, or when
+    // the contraction rho of the last two corrections (refinement converges
+    // linearly) predicts the remaining error rho / (1 - rho) |d| below it
+    const double rho = (sweep >= 2 && dprev > 0.0) ? dm / dprev : 1.0;
+    const bool conv = dm <= rtol * xm || (rho < 0.5 && rho * dm <= rtol * xm * (1.0 - rho));
+    if (!done && gxf && conv) {
       status = sweep;
       done = true;
     }
+    dprev = dm;
   }
   if (live && gl == 0) info[s] = status;
   if (live && status > 0)
@@ -947,7 +954,7 @@ __global__ __launch_bounds__(256) void solve_kernel(int N, int64_t n, int64_t ld
                                                     const double* __restrict__ rbuf, double* __restrict__ xs,
                                                     double* __restrict__ xout, const int* __restrict__ list,
                                                     const int* __restrict__ count, int* __restrict__ status,
-                                                    int sweep, double rtol) {
+                                                    int sweep, double rtol, double* __restrict__ dprev) {
   extern __shared__ char smem[];
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
   const int64_t slot = (int64_t)blockIdx.x * 4 + wv;
@@ -1010,7 +1017,15 @@ __global__ __launch_bounds__(256) void solve_kernel(int N, int64_t n, int64_t ld
     xmax = fmax(xmax, __shfl_xor(xmax, o));
   }
   fin = __all(fin);
-  if (lane == 0 && sweep > 0 && fin && dmax <= rtol * xmax) status[st] = sweep;
+  if (lane == 0 && sweep > 0) {
+    // converged when the correction is below rtol of the solution, or when
+    // the contraction rho of the last two corrections (refinement converges
+    // linearly) predicts the remaining error rho / (1 - rho) |d| below it
+    const double dp = sweep >= 2 ? dprev[st] : 0.0;
+    const double rho = dp > 0.0 ? dmax / dp : 1.0;
+    if (fin && (dmax <= rtol * xmax || (rho < 0.5 && rho * dmax <= rtol * xmax * (1.0 - rho)))) status[st] = sweep;
+    dprev[st] = dmax;
+  }
 }
 
 // r = b - (I - h gamma J) x in FP64.  grid (ceil(n / 256), ceil(N / 8)): one
@@ -1106,7 +1121,7 @@ size_t small_keep_bytes(int N, int64_t n) {
 
 struct WsLayout {
   size_t a32 = 0, a64 = 0, piv = 0, piv64 = 0, sing = 0, status = 0, fbstatus = 0, xs = 0, rbuf = 0, list = 0,
-         count = 0, total = 0;
+         count = 0, dprev = 0, total = 0;
 };
 
 WsLayout ws_layout(int N, int64_t n, int mode) {
@@ -1126,6 +1141,7 @@ WsLayout ws_layout(int N, int64_t n, int mode) {
     L.rbuf = take((size_t)n * N * sizeof(double));
     L.list = take((size_t)n * sizeof(int));
     L.count = take(sizeof(int));
+    L.dprev = take((size_t)n * sizeof(double));     // previous sweep's correction per state
   }
   L.total = off;
   return L;
@@ -1150,7 +1166,7 @@ hipError_t run_direct(int N, int64_t n, int64_t ld, const double* jac, const dou
   }
   hipLaunchKernelGGL((solve_kernel<T, false>), dim3((unsigned)((n + 3) / 4)), dim3(256), 4 * N * sizeof(T), st, N, n, ld,
                      (const T*)A, (const int*)piv, rhs, (const double*)nullptr, (double*)nullptr, x, list, count, status, 0,
-                     0.0);
+                     0.0, (double*)nullptr);
   return hipGetLastError();
 }
 
@@ -1296,6 +1312,7 @@ pyjac_status pyjac_newton_factor_solve(const pyjac_mech* m, int64_t n, int64_t l
     double* rbuf = reinterpret_cast<double*>(w + L.rbuf);
     int* list = reinterpret_cast<int*>(w + L.list);
     int* count = reinterpret_cast<int*>(w + L.count);
+    double* dprev = reinterpret_cast<double*>(w + L.dprev);
     hipLaunchKernelGGL(init_status_kernel, dim3(g1), dim3(256), 0, st, n, status, xs, N);
     if (reuse) hipLaunchKernelGGL(copy_status_kernel, dim3(g1), dim3(256), 0, st, n, (const int*)sing, status);
     hipLaunchKernelGGL(copy_rhs_kernel, dim3(g1), dim3(256), 0, st, N, n, ld, rhs, rbuf);
@@ -1318,7 +1335,7 @@ pyjac_status pyjac_newton_factor_solve(const pyjac_mech* m, int64_t n, int64_t l
                            rbuf, (const int*)status);
       hipLaunchKernelGGL((solve_kernel<float, true>), dim3(gs), dim3(256), 4 * N * sizeof(float), st, N, n, ld,
                          (const float*)A32, (const int*)piv, (const double*)nullptr, (const double*)rbuf, xs,
-                         (double*)nullptr, (const int*)nullptr, (const int*)nullptr, status, sweep, rtol);
+                         (double*)nullptr, (const int*)nullptr, (const int*)nullptr, status, sweep, rtol, dprev);
     }
     // FP64 re-solve of the states that did not converge (or whose FP32 factor was singular)
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, count);
