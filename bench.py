@@ -532,6 +532,8 @@ def main() -> int:
     ap.add_argument("--states", type=int, default=None, help="override the batch size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-pasr", action="store_true", help="skip the PaSR leg (its integrator launches the "
+                    "Jacobian kernel on 10,000-state batches, which would mix into a profile's averages)")
     ap.add_argument("--serving-requests", type=int, default=120)
     ap.add_argument("--variant", type=str, default=None, help="Jacobian launch shape TS,NT")
     ap.add_argument("--jacobian-only-config", type=int, default=None, metavar="ID",
@@ -677,8 +679,9 @@ def main() -> int:
     log("concentration-form Jacobian timed")
     cs_info = cs_leg(M, d_phi, d_p, min(n, 8192), jac_med, n, torch)
     log("complex-step Jacobian timed")
-    pasr_info = pasr_leg(mech, M, torch)
-    log("PaSR driver and Jacobian on its states timed")
+    pasr_info = None if args.no_pasr else pasr_leg(mech, M, torch)
+    if pasr_info is not None:
+        log("PaSR driver and Jacobian on its states timed")
 
     out.update({
         "metric": "Jacobian evals/s (FP64, <=1e-10 rel err vs oracle) + p50/p99 request latency",
