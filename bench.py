@@ -112,7 +112,7 @@ def jacobian_only(cfg: int, steps: int) -> int:
     sizes; the benchmark step itself runs the 53-species workload)."""
     import torch
     from paper_1605_03262_amd import Mechanism
-    from synth import CONFIGS, config_mechanism, config_states
+    from synth import WORKLOADS, config_mechanism, config_states
     mech = config_mechanism(cfg)
     phi, p = config_states(cfg)
     N, n = mech.n_species, phi.shape[1]
@@ -157,7 +157,7 @@ def jacobian_only(cfg: int, steps: int) -> int:
         sdirk[name] = {"ms_median": smed, "state_steps_per_s": n / (smed * 1e-3)}
         del sws
     by = n * (8.0 * N * N + 8.0 * (N + 1))
-    print(json.dumps({"workload": CONFIGS[cfg]["name"], "n_states": n, "n_species": N, "newton": newton,
+    print(json.dumps({"workload": WORKLOADS[cfg]["name"], "n_states": n, "n_species": N, "newton": newton,
                       "sdirk3_step": sdirk,
                       "jacobian_ms_median": med, "jacobian_evals_per_s": n / (med * 1e-3),
                       "hbm_frac": by / (med * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -190,8 +190,8 @@ def write_traffic(fetch_dir: str, write_dir: str) -> int:
     (COPY_BYTES read and written).  Stored with a hash of the kernel source,
     so that a later kernel change invalidates them."""
     import re
-    from synth import CONFIGS
-    out = {"kernel_source_hash": kernel_source_hash(), "workload": CONFIGS[CFG]["name"],
+    from synth import WORKLOADS
+    out = {"kernel_source_hash": kernel_source_hash(), "workload": WORKLOADS[CFG]["name"],
            "copy_bytes": COPY_BYTES, "unit": "bytes per launch of 100,000 states", "shapes": {},
            "commands": [PMC_COMMAND.format(c="FETCH_SIZE", d=os.path.basename(os.path.normpath(fetch_dir)), o="f"),
                         PMC_COMMAND.format(c="WRITE_SIZE", d=os.path.basename(os.path.normpath(write_dir)), o="w")]}
@@ -558,10 +558,10 @@ def main() -> int:
     import numpy as np
     import torch
     from paper_1605_03262_amd import NEWTON_FP64, NEWTON_MIXED, Mechanism, _lib
-    from synth import (CONFIGS, NEWTON_GAMMA, conditioned_steps, config_mechanism, config_states,
+    from synth import (WORKLOADS, NEWTON_GAMMA, conditioned_steps, config_mechanism, config_states,
                        draw_newton_inputs)
 
-    c = CONFIGS[CFG]
+    c = WORKLOADS[CFG]
     mech = config_mechanism(CFG)
     phi, p = config_states(CFG, args.states)
     n, N = phi.shape[1], mech.n_species

@@ -543,7 +543,7 @@ def _c1_mix(n_total: int) -> Dict[str, int]:
             "chemact_lindemann": ca_l, "chemact_troe": ca_t, "chemact_sri": ca_s}
 
 
-CONFIGS = {
+WORKLOADS = {
     0: dict(name="h2_shaped_13sp_27rxn", n_species=13, n_reactions=27,
             elements=["H", "O", "N", "Ar"], bounds={"H": 2, "O": 2, "N": 1},
             mix={"elementary": 20, "thirdbody": 5, "falloff_troe": 2},
@@ -569,7 +569,7 @@ STATE_SEED_BASE = 3262
 
 
 def config_mechanism(cfg_id: int) -> Mechanism:
-    c = CONFIGS[cfg_id]
+    c = WORKLOADS[cfg_id]
     return make_mechanism(MECH_SEED_BASE + cfg_id, c["n_species"], c["n_reactions"],
                           c["elements"], c["bounds"], c["mix"], name=c["name"])
 

@@ -10,7 +10,7 @@ from typing import Tuple
 
 import numpy as np
 
-from .mechgen import ATM, CONFIGS, STATE_SEED_BASE
+from .mechgen import ATM, WORKLOADS, STATE_SEED_BASE
 
 NEWTON_GAMMA = 0.4358665
 
@@ -29,7 +29,7 @@ def draw_states(seed: int, n_species: int, n_states: int, T=(800.0, 2200.0),
 
 
 def config_states(cfg_id: int, n_states: int | None = None):
-    c = CONFIGS[cfg_id]
+    c = WORKLOADS[cfg_id]
     n = c["n_states"] if n_states is None else n_states
     return draw_states(STATE_SEED_BASE + cfg_id, c["n_species"], n, c["T"],
                        c["P_atm"], c["dirichlet"])

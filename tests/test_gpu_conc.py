@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from conftest import ALL_KINDS, BLENDED, species_collider_mech, tiny, zero_collider_states
-from synth import CONFIGS, config_mechanism, config_states, draw_states
+from synth import WORKLOADS, config_mechanism, config_states, draw_states
 from test_gpu_parity import JAC_TOL, enorm_per_state
 from test_oracle_conc_pins import conc_states
 

@@ -18,7 +18,7 @@ import pytest
 
 from conftest import BLENDED, species_collider_mech, zero_collider_states
 from equilibrium import equilibrium_states
-from synth import (CONFIGS, NEWTON_GAMMA, conditioned_steps, config_mechanism, config_states,
+from synth import (WORKLOADS, NEWTON_GAMMA, conditioned_steps, config_mechanism, config_states,
                    draw_newton_inputs, draw_states, make_mechanism)
 from test_gpu_parity import JAC_TOL, check_jac, check_rates, gpu_jac, gpu_mech, gpu_rates
 
@@ -108,7 +108,7 @@ def test_reactive_last_species_full_size_mechanism(torch, Ref):
     """53 species / 325 reactions in the methane-shaped mix, but the last
     species (whose mass fraction is implied) takes part in reactions, so every
     placeholder-row term of Sec. 3.2 is exercised at full mechanism size."""
-    c = CONFIGS[1]
+    c = WORKLOADS[1]
     mech = make_mechanism(1605 + 101, c["n_species"], c["n_reactions"], c["elements"], c["bounds"],
                           c["mix"], reactive_last=True, name="reactive_last_53")
     L = mech.n_species - 1
@@ -179,7 +179,7 @@ def test_newton_full_batch_sampled(torch, Ref, cfg):
     from paper_1605_03262_amd import NEWTON_FP64, NEWTON_MIXED, Mechanism
     mech = config_mechanism(cfg)
     N = mech.n_species
-    n = CONFIGS[cfg]["n_states"]
+    n = WORKLOADS[cfg]["n_states"]
     n_base = 96 if cfg == 2 else 24
     phi, p = config_states(cfg, n_base)
     Jb = Ref(text=mech.to_text()).eval_jacobian(phi, p)
