@@ -95,7 +95,7 @@ Variant pick(const PackedMech& P, bool jac, size_t max_lds) {
 }
 
 // Shapes compiled for the concentration-form Jacobian, most preferred first.
-const int kConcShapes[][2] = {{16, 1024}, {8, 1024}, {8, 512}, {4, 1024}, {4, 512}, {2, 512}};
+const int kConcShapes[][2] = {{16, 1024}, {8, 1024}, {8, 512}, {4, 1024}, {4, 512}, {2, 512}, {8, 256}, {4, 256}};
 
 bool conc_fits(const PackedMech& P, Variant v, size_t max_lds) {
   return kpt_of(P.N, v.ts, v.nt) <= 8 && conc_lds_bytes(P.N, P.NR, P.NG, v.ts, v.nt) <= max_lds;

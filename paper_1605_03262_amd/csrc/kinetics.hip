@@ -1199,6 +1199,8 @@ hipError_t launch_conc(int TS, int NT, const MechDev& md, int64_t n, int64_t ld,
     return hipErrorInvalidValue;                                                       \
   }
   PYJAC_CONC(16, 1024)
+  PYJAC_CONC(8, 256)
+  PYJAC_CONC(4, 256)
   PYJAC_CONC(8, 512)
   PYJAC_CONC(8, 1024)
   PYJAC_CONC(4, 512)

@@ -876,9 +876,9 @@ size_t grp_lds_bytes(int N, int S) {
   return (size_t)(kGrpStage / WS) * N * WS * sizeof(double);
 }
 
-// up to two SW x NM buffers + the stage + SW x NM slack for the masked
-// reads past the last staged row
-size_t small_lds(int N, int NM, int SW) { return ((size_t)SRB * N * SW + 3 * (size_t)SW * NM) * sizeof(double); }
+// the SW x NM solution buffer + the stage + SW x NM slack for the reads
+// past the last staged row
+size_t small_lds(int N, int NM, int SW) { return ((size_t)SRB * N * SW + 2 * (size_t)SW * NM) * sizeof(double); }
 
 template <int NM>
 hipError_t launch_small_t(int N, int64_t n, int64_t ld, const double* jac, const double* h, double gamma,

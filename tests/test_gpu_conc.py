@@ -151,7 +151,7 @@ def test_conc_shapes_and_batch_independence(torch):
     assert np.array_equal(base, gpu_conc(torch, M, c, ld=311))
     assert np.array_equal(base[:, 17:18], gpu_conc(torch, M, c[:, 17:18]))
     tried = 0
-    for ts, nt in ((16, 1024), (8, 512), (8, 1024), (4, 512), (4, 1024), (2, 512)):
+    for ts, nt in ((16, 1024), (8, 512), (8, 1024), (4, 512), (4, 1024), (2, 512), (8, 256), (4, 256)):
         try:
             M.set_variant(2, ts, nt)
         except Exception:
