@@ -122,42 +122,40 @@ class PaSR:
         finite, physical (mass fractions in [-1e-6, 1 + 1e-6], 200 K < T <
         6000 K, |dT| < 300 K) and its simplified Newton iterations converged
         (last increment <= 1e-4 of the step's change); otherwise the particle
-        retries with a quarter
-        of the step; after a kept step its step size doubles (up to dt).  A
-        particle that exhausts the tries keeps its state (counted in
-        self.frozen)."""
+        retries with a quarter of the step; after a kept step its step size
+        doubles (up to dt).  A particle that exhausts the tries keeps the
+        progress of its kept steps (counted in self.frozen).  The bookkeeping
+        stays on the device; the host reads one count per try."""
         torch = _torch()
         n = self.n
-        t_rem = np.full(n, dt)
+        dev = self.phi.device
+        t_rem = torch.full((n,), dt, dtype=torch.float64, device=dev)
         if not hasattr(self, "_hp"):
-            self._hp = np.full(n, dt / self.react_steps)
-        h = np.minimum(self._hp, dt)
+            self._hp = torch.full((n,), dt / self.react_steps, dtype=torch.float64, device=dev)
+        h = torch.clamp(self._hp, max=dt)
         out = torch.empty_like(self.phi)
         for _ in range(max_tries):
             active = t_rem > 1e-9 * dt
-            if not active.any():
+            if not bool(active.any()):
                 break
-            hs = np.where(active, np.minimum(h, t_rem), 0.0)
-            self._h.copy_(torch.from_numpy(hs))
+            hs = torch.where(active, torch.minimum(h, t_rem), torch.zeros_like(h))
+            self._h.copy_(hs)
             _, dn = self.mech.sdirk3_step(self.phi, self.p, self._h, newton_iters=self.newton_iters,
                                           mode=NEWTON_FP64, out=out, workspace=self._ws)
-            new = out.cpu().numpy()
-            old = self.phi.cpu().numpy()
-            dmax = dn.cpu().numpy().max(axis=0)
+            new, old = out, self.phi
+            dmax = dn.max(dim=0).values
             Y = new[1:]
-            # converged: the last Newton increment is small against the step's change
-            change = np.abs(new - old).max(axis=0)
-            ok = (np.isfinite(new).all(axis=0) & np.isfinite(dmax) & (dmax <= 1e-4 * change + 1e-12)
-                  & (Y > -1e-6).all(axis=0) & (Y < 1 + 1e-6).all(axis=0) & (Y.sum(axis=0) < 1 + 1e-6)
-                  & (new[0] > 200.0) & (new[0] < 6000.0) & (np.abs(new[0] - old[0]) < 300.0))
+            change = (new - old).abs().max(dim=0).values
+            ok = (torch.isfinite(new).all(dim=0) & torch.isfinite(dmax) & (dmax <= 1e-4 * change + 1e-12)
+                  & (Y > -1e-6).all(dim=0) & (Y < 1 + 1e-6).all(dim=0) & (Y.sum(dim=0) < 1 + 1e-6)
+                  & (new[0] > 200.0) & (new[0] < 6000.0) & ((new[0] - old[0]).abs() < 300.0))
             keep = active & ok
-            merged = np.where(keep[None, :], new, old)
-            self.phi.copy_(torch.from_numpy(merged))
-            t_rem = np.where(keep, t_rem - hs, t_rem)
-            h = np.where(keep, np.minimum(2 * h, dt), np.where(active, h / 4, h))
+            self.phi = torch.where(keep[None, :], new, old)
+            t_rem = torch.where(keep, t_rem - hs, t_rem)
+            h = torch.where(keep, torch.clamp(2 * h, max=dt), torch.where(active, h / 4, h))
         stuck = t_rem > 1e-9 * dt
-        self.frozen = getattr(self, "frozen", 0) + int(stuck.sum())
-        self._hp = np.maximum(h, 1e-12)
+        self.frozen = getattr(self, "frozen", 0) + int(stuck.sum().item())
+        self._hp = torch.clamp(h, min=1e-12)
 
     def run(self, n_res: float):
         """Advance n_res residence times."""

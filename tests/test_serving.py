@@ -137,6 +137,15 @@ def test_work_list_launch_equals_single_launches():
     torch.cuda.synchronize()
     for (out, _, _), e in zip(outs, expect):
         assert torch.equal(out, e)
+    # the same with a 256-thread shape (its own register budget)
+    for M in mechs:
+        M.set_variant(1, 4, 256)
+    for out, _, _ in outs:
+        out.fill_(float("nan"))
+    _lib.pyjac_eval_jacobian_multi(items, stream)
+    torch.cuda.synchronize()
+    for (out, _, _), e in zip(outs, expect):
+        assert torch.equal(out, e)
     mechs[1].set_variant(1, 4, 512)
     with pytest.raises(PyjacError):
         _lib.pyjac_eval_jacobian_multi(items, stream)
