@@ -605,10 +605,11 @@ __device__ __forceinline__ void tile_body(const MechDev& md, unsigned tile, int6
     const double vj = md.vcol[j];
     double TR;
     if constexpr (!SPLIT) {
-      // Column j, every row streamed: terms and one marker per row, read
-      // kColBatch records at a time with independent loads; every record is
-      // evaluated without branching (markers and padding have coef = 0) and a
-      // marker finishes the current row and starts the next.
+      // Column j, every row streamed: each row's terms, the last one marked
+      // (a row without terms is a marker alone), read kColBatch records at a
+      // time with independent loads; every record is evaluated without
+      // branching (markers and padding have coef = 0) and a marked record
+      // finishes the current row after its own term and starts the next.
       // A lane past the end of the batch computes the last state's values
       // (it read that state's inputs) and stores them to that state's
       // elements, the same values the live lane stores, so no store needs a

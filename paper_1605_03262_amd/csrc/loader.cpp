@@ -480,12 +480,19 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
       for (int j = 0; j < N - 1; ++j) {
         P.col_start.push_back((int)P.colrec.size());
         for (int k = 0; k < N; ++k) {
+          const size_t first = P.colrec.size();
           for (; t < terms.size() && terms[t].j == j && terms[t].k == k; ++t)
             P.colrec.push_back(ColRec{terms[t].coef, N + 1 + terms[t].src, terms[t].x});
-          // end of row k (the placeholder row N - 1 has no marker: the kernel
-          // finishes it after the stream); markers and padding address X[N] = 1
-          // and contribute 0
-          if (k < N - 1) P.colrec.push_back(ColRec{0.0, N, N | (N << 15) | kColMark});
+          // end of row k (the placeholder row N - 1 has none: the kernel
+          // finishes it after the stream): the mark bit on the row's last term,
+          // or a marker of its own for a row without terms; markers and padding
+          // address X[N] = 1 and contribute 0
+          if (k < N - 1) {
+            if (P.colrec.size() > first)
+              P.colrec.back().x |= kColMark;
+            else
+              P.colrec.push_back(ColRec{0.0, N, N | (N << 15) | kColMark});
+          }
         }
         while (P.colrec.size() % kColBatch) P.colrec.push_back(ColRec{0.0, N, N | (N << 15)});
       }

@@ -55,12 +55,13 @@ static_assert(sizeof(RxnRec) == 256, "RxnRec must stay 256 bytes");
 // One entry of a Jacobian column stream.  Every entry contributes
 // coef * X[src] * X[x & 0x7FFF] * X[(x >> 15) & 0x7FFF] to the current element,
 // where X[0..N] are the concentrations (X[N] = 1) and the rate products P
-// follow directly, so src = N + 1 + (index into P).  A marker has bit kColMark
-// set in x and coef = 0; padding has coef = 0 and src = N.  Two forms:
+// follow directly, so src = N + 1 + (index into P).  An entry with bit
+// kColMark set in x ends a row after its own contribution; a marker is such an
+// entry with coef = 0; padding has coef = 0 and src = N.  Two forms:
 //  * every row (col_split = 0): for rows k = 0..N-1 in order, the terms of
-//    (k, j) and, for k < N - 1, a marker (src = N) that ends row k (the
-//    placeholder row N - 1 is finished after the stream); padding to a
-//    multiple of kColBatch.
+//    (k, j); for k < N - 1 the row's last term carries the mark, and a row
+//    without terms is a marker (src = N) alone (the placeholder row N - 1 is
+//    finished after the stream); padding to a multiple of kColBatch.
 //  * present rows only (col_split = 1): bit k of the column's col_flags words
 //    marks row k as present (streamed); the other rows hold the dense part
 //    alone.  The stream is a marker, then for each present row in ascending
