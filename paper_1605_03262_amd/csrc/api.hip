@@ -124,6 +124,7 @@ pyjac_status upload(pyjac_mech* m) {
   append(blob, P.spg_ent, o);
   append(blob, P.col_start, o); append(blob, P.colrec, o); append(blob, P.col_order, o);
   append(blob, P.col_flags, o);
+  append(blob, P.col_item, o); append(blob, P.col_join, o);
   append(blob, P.cv_col_start, o); append(blob, P.cv_colrec, o); append(blob, P.cv_col_order, o);
   append(blob, P.cv_colptr, o);
   if (hipMalloc(&m->dmem, blob.size()) != hipSuccess) return fail(PYJAC_E_NOMEM, "hipMalloc of mechanism tables failed");
@@ -142,6 +143,8 @@ pyjac_status upload(pyjac_mech* m) {
   d.spg_ent = D((const int*)0);
   d.col_start = D((const int*)0); d.colrec = D((const ColRec*)0); d.col_order = D((const int*)0);
   d.col_flags = D((const uint32_t*)0);
+  d.col_item = D((const ColItem*)0); d.col_join = D((const ColJoin*)0);
+  d.n_col_item = (int)P.col_item.size(); d.n_col_join = (int)P.col_join.size();
   d.cv_col_start = D((const int*)0); d.cv_colrec = D((const ColRec*)0); d.cv_col_order = D((const int*)0);
   d.cv_colptr = D((const int*)0);
   d.spg_chunk = nullptr;

@@ -600,11 +600,25 @@ __device__ __forceinline__ void tile_body(const MechDev& md, unsigned tile, int6
   const double* aN = nasa_coeffs(md, N - 1, T);
   const double cpN = (aN[0] + T * (aN[1] + T * (aN[2] + T * (aN[3] + aN[4] * T)))) * kR * md.invW[N - 1];
   const double* Xb = lds + (size_t)L.X * TS + s;
-  for (int jc = g; jc < N - 1; jc += Gr) {
-    const int j = md.col_order[jc];
-    const double vj = md.vcol[j];
-    double TR;
-    if constexpr (!SPLIT) {
+  // temperature-row element of column j from TR = sum_k h_k J[k][j] (Sec. 3.2)
+  auto finish = [&](int j, double TR) {
+    const double* aj = nasa_coeffs(md, j, T);
+    const double cpj = (aj[0] + T * (aj[1] + T * (aj[2] + T * (aj[3] + aj[4] * T)))) * kR * md.invW[j];
+    if (live) jac[(int64_t)(j + 1) * ld + sg] = -(-(cpj - cpN) * irho * icp * Shw + TR) * icp;
+  };
+  if constexpr (!SPLIT) {
+    // Column segments, longest first, dealt to the groups in snake order
+    // (forward on even passes, backward on odd ones) so that a group with a
+    // long segment gets a short one next.  A column cut into several segments
+    // leaves one partial temperature-row sum per segment in the rows of the
+    // phase-C sums (free by now); after a barrier they are added in row order.
+    const int nit = md.n_col_item;
+    for (int m = 0; m * Gr < nit; ++m) {
+      const int it = m * Gr + ((m & 1) ? Gr - 1 - g : g);
+      if (it >= nit) continue;
+      const ColItem I = md.col_item[it];
+      const int j = I.j;
+      const double vj = md.vcol[j];
       // Column j, every row streamed: each row's terms, the last one marked
       // (a row without terms is a marker alone), read kColBatch records at a
       // time with independent loads; every record is evaluated without
@@ -614,15 +628,15 @@ __device__ __forceinline__ void tile_body(const MechDev& md, unsigned tile, int6
       // (it read that state's inputs) and stores them to that state's
       // elements, the same values the live lane stores, so no store needs a
       // condition.
-      const ColRec* rec = md.colrec + md.col_start[j];
-      const int cnt = md.col_start[j + 1] - md.col_start[j];
-      double* outp = jac + (int64_t)(N + j + 1) * ld + sl;       // element (1, j+1)
+      const ColRec* rec = md.colrec + I.rec;
+      const int cnt = I.cnt;
+      double* outp = jac + (int64_t)((I.k0 + 1) * N + j + 1) * ld + sl;   // element (k0+1, j+1)
       const int64_t rstride = (int64_t)N * ld;
-      TR = 0.0;
+      double TR = 0.0;
       // row k's (A_k, B_k) and h_k; the arrays hold a slack row N, so the
       // look-ahead of row k + 1 needs no clamp (its value is then never used)
-      const double2* wab = WAB;
-      const double* hp = H;
+      const double2* wab = WAB + I.k0 * TS;
+      const double* hp = H + I.k0 * TS;
       double val = wab[0].x * vj + wab[0].y;
       double hk = hp[0];
       double2 abn = wab[TS];
@@ -659,8 +673,31 @@ __device__ __forceinline__ void tile_body(const MechDev& md, unsigned tile, int6
 #pragma unroll
         for (int u = 0; u < kColBatch; ++u) r[u] = nx[u];
       }
-      TR += hk * val;                  // the placeholder row N - 1 (not stored)
-    } else {
+      // the placeholder row N - 1 (not stored) ends the column's last segment;
+      // after an earlier segment the open row belongs to the next one
+      if (I.last) TR += hk * val;
+      if (I.slot < 0)
+        finish(j, TR);
+      else
+        redc[I.slot * TS] = TR;
+    }
+    if (md.n_col_join > 0) {
+      __syncthreads();
+      for (int c = g; c < md.n_col_join; c += Gr) {
+        const ColJoin Jn = md.col_join[c];
+        double TR = redc[Jn.slot0 * TS];
+        for (int q = 1; q < Jn.nslot; ++q) TR += redc[(Jn.slot0 + q) * TS];
+        finish(Jn.j, TR);
+      }
+    }
+  } else {
+    // columns, longest first, dealt to the groups in snake order
+    for (int m = 0; m * Gr < N - 1; ++m) {
+      const int jc = m * Gr + ((m & 1) ? Gr - 1 - g : g);
+      if (jc >= N - 1) continue;
+      const int j = md.col_order[jc];
+      const double vj = md.vcol[j];
+      double TR;
       double* colp = jac + (int64_t)(N + j + 1) * ld + sg;       // element (1, j+1): row k = 0
       const int64_t rstride = (int64_t)N * ld;
       const int FW = colFlagWords(N);
@@ -743,10 +780,8 @@ __device__ __forceinline__ void tile_body(const MechDev& md, unsigned tile, int6
         for (int u = 0; u < kColBatch; ++u) ra[u] = rec[b + 2 * kColBatch + u];
         batch(rb);
       }
+      finish(j, TR);
     }
-    const double* aj = nasa_coeffs(md, j, T);
-    const double cpj = (aj[0] + T * (aj[1] + T * (aj[2] + T * (aj[3] + aj[4] * T)))) * kR * md.invW[j];
-    if (live) jac[(int64_t)(j + 1) * ld + sg] = -(-(cpj - cpN) * irho * icp * Shw + TR) * icp;
   }
 }
 

@@ -15,6 +15,7 @@
 // reverse A b Ta.  SI-kmol units; Ta is the activation temperature in K.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -282,6 +283,75 @@ uint64_t fnv1a(const std::string& s) {
 
 int pack_side(int sp, int nu) { return sp | (nu << 16); }
 
+// A piece of a Jacobian column stream: rows [k0, k1) of column j, len records.
+struct ColSeg {
+  int j, k0, k1, len;
+};
+
+// Longest segment a group would stream when segments, longest first, are dealt
+// to `groups` groups in snake order (the order of the tile kernel's phase D),
+// each segment costing its padded length plus a fixed set-up.
+int snake_makespan(std::vector<int> len, int groups) {
+  std::sort(len.rbegin(), len.rend());
+  std::vector<int> load(groups, 0);
+  for (size_t i = 0; i < len.size(); ++i) {
+    const int m = (int)(i / groups), r = (int)(i % groups);
+    load[(m & 1) ? groups - 1 - r : r] += (len[i] + kColBatch - 1) / kColBatch * kColBatch + 8;
+  }
+  return *std::max_element(load.begin(), load.end());
+}
+
+// Splits the every-row column streams at row boundaries so that 64 groups
+// (the group count of the usual launch shapes) finish phase D together: the
+// longest segment is halved while that lowers the snake makespan, as long as
+// the partial sums of the split columns fit the 2N rows the tile kernel keeps
+// for them.  The split depends on the mechanism only, never on the launch
+// shape, so results stay identical across shapes.
+std::vector<ColSeg> split_columns(const std::vector<std::vector<std::vector<ColRec>>>& rows, int N) {
+  constexpr int kGroups = 64, kMinSplit = 32;
+  std::vector<ColSeg> segs;
+  for (int j = 0; j < N - 1; ++j) {
+    int len = 0;
+    for (int k = 0; k < N; ++k) len += (int)rows[j][k].size();
+    segs.push_back(ColSeg{j, 0, N, len});
+  }
+  auto lens = [&](const std::vector<ColSeg>& v) {
+    std::vector<int> l;
+    for (auto& g : v) l.push_back(g.len);
+    return l;
+  };
+  auto slots = [&](const std::vector<ColSeg>& v) {
+    std::vector<int> n(N, 0);
+    for (auto& g : v) ++n[g.j];
+    int s = 0;
+    for (int c : n) s += c > 1 ? c : 0;
+    return s;
+  };
+  std::vector<ColSeg> best = segs;
+  int best_ms = snake_makespan(lens(segs), kGroups);
+  for (;;) {
+    int w = -1;
+    for (int i = 0; i < (int)segs.size(); ++i)
+      if (segs[i].k1 - segs[i].k0 > 1 && segs[i].len >= kMinSplit && (w < 0 || segs[i].len > segs[w].len)) w = i;
+    if (w < 0) break;
+    // the row boundary that best halves the segment
+    const ColSeg g = segs[w];
+    int acc = 0, cut = g.k0 + 1, cut_acc = 0, err = 1 << 30;
+    for (int k = g.k0; k < g.k1 - 1; ++k) {
+      acc += (int)rows[g.j][k].size();
+      const int e = std::abs(2 * acc - g.len);
+      if (e < err) { err = e; cut = k + 1; cut_acc = acc; }
+    }
+    segs[w] = ColSeg{g.j, g.k0, cut, cut_acc};
+    segs.push_back(ColSeg{g.j, cut, g.k1, g.len - cut_acc});
+    if (slots(segs) > 2 * N) break;
+    const int ms = snake_makespan(lens(segs), kGroups);
+    if (ms < best_ms) { best_ms = ms; best = segs; }
+    if ((int)segs.size() >= 4 * kGroups) break;
+  }
+  return best;
+}
+
 }  // namespace
 
 int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
@@ -476,28 +546,46 @@ int build_tables(const std::string& text, PackedMech& P, std::string& msg) {
       P.col_split = 2 * pairs < (long long)(N - 1) * N ? 1 : 0;
     }
     if (!P.col_split) {
-      size_t t = 0;
+      // records of every row of every column: the row's terms, the last one
+      // carrying the mark for k < N - 1, or a marker alone for a row without
+      // terms (the placeholder row N - 1 has none: the kernel finishes it after
+      // the stream); markers and padding address X[N] = 1 and contribute 0
+      std::vector<std::vector<std::vector<ColRec>>> rows(N - 1, std::vector<std::vector<ColRec>>(N));
+      for (size_t t = 0; t < terms.size(); ++t)
+        rows[terms[t].j][terms[t].k].push_back(ColRec{terms[t].coef, N + 1 + terms[t].src, terms[t].x});
+      for (int j = 0; j < N - 1; ++j)
+        for (int k = 0; k < N - 1; ++k) {
+          if (rows[j][k].empty()) rows[j][k].push_back(ColRec{0.0, N, N | (N << 15)});
+          rows[j][k].back().x |= kColMark;
+        }
+      const std::vector<ColSeg> segs = split_columns(rows, N);
+      // emission: each column's segments in row order, each padded to a
+      // multiple of kColBatch; a column in several segments gets consecutive
+      // slots for its partial temperature-row sums, added in row order
+      P.col_item.clear();
+      P.col_join.clear();
+      int slot = 0;
       for (int j = 0; j < N - 1; ++j) {
         P.col_start.push_back((int)P.colrec.size());
-        for (int k = 0; k < N; ++k) {
-          const size_t first = P.colrec.size();
-          for (; t < terms.size() && terms[t].j == j && terms[t].k == k; ++t)
-            P.colrec.push_back(ColRec{terms[t].coef, N + 1 + terms[t].src, terms[t].x});
-          // end of row k (the placeholder row N - 1 has none: the kernel
-          // finishes it after the stream): the mark bit on the row's last term,
-          // or a marker of its own for a row without terms; markers and padding
-          // address X[N] = 1 and contribute 0
-          if (k < N - 1) {
-            if (P.colrec.size() > first)
-              P.colrec.back().x |= kColMark;
-            else
-              P.colrec.push_back(ColRec{0.0, N, N | (N << 15) | kColMark});
-          }
+        std::vector<ColSeg> mine;
+        for (const ColSeg& g : segs) if (g.j == j) mine.push_back(g);
+        std::sort(mine.begin(), mine.end(), [](const ColSeg& a, const ColSeg& b) { return a.k0 < b.k0; });
+        const bool joined = mine.size() > 1;
+        if (joined) P.col_join.push_back(ColJoin{j, slot, (int)mine.size(), 0});
+        for (size_t q = 0; q < mine.size(); ++q) {
+          const int rec = (int)P.colrec.size();
+          for (int k = mine[q].k0; k < mine[q].k1; ++k)
+            P.colrec.insert(P.colrec.end(), rows[j][k].begin(), rows[j][k].end());
+          while (P.colrec.size() % kColBatch) P.colrec.push_back(ColRec{0.0, N, N | (N << 15)});
+          P.col_item.push_back(ColItem{j, mine[q].k0, rec, (int)P.colrec.size() - rec, joined ? slot++ : -1,
+                                       mine[q].k1 == N ? 1 : 0, 0, 0});
         }
-        while (P.colrec.size() % kColBatch) P.colrec.push_back(ColRec{0.0, N, N | (N << 15)});
       }
+      // longest first: the groups of a wavefront stream in lockstep
+      std::stable_sort(P.col_item.begin(), P.col_item.end(),
+                       [](const ColItem& a, const ColItem& b) { return a.cnt > b.cnt; });
       P.col_start.push_back((int)P.colrec.size());
-      // one batch of slack: the kernel reads one batch past a column's stream
+      // one batch of slack: the kernel reads one batch past a segment's stream
       for (int u = 0; u < kColBatch; ++u) P.colrec.push_back(ColRec{0.0, N, N | (N << 15)});
     } else {
       size_t t = 0;

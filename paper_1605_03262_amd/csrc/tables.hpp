@@ -77,6 +77,20 @@ struct alignas(16) ColRec {
 constexpr int kColMark = 1 << 30;
 constexpr int kColBatch = 4;
 
+// Every-row form: a column's stream may be cut at row boundaries into
+// segments that separate groups stream.  Segment: rows [k0, ...) of column j,
+// records [rec, rec + cnt) (cnt a multiple of kColBatch); last = 1 when it
+// holds the placeholder row N - 1.  slot < 0: the column is one segment and
+// its temperature-row element is finished at once; otherwise the partial
+// temperature-row sum goes to that slot and the column's ColJoin adds its
+// nslot slots (slot0 ...) in row order.
+struct alignas(16) ColItem {
+  int j, k0, rec, cnt, slot, last, pad0, pad1;
+};
+struct alignas(16) ColJoin {
+  int j, slot0, nslot, pad;
+};
+
 // Host-side packed tables (sorted reaction order).
 struct PackedMech {
   int N = 0, NR = 0, NG = 0;
@@ -92,6 +106,8 @@ struct PackedMech {
   std::vector<int> col_start;                             // [N] stream offsets per column
   std::vector<ColRec> colrec;
   std::vector<int> col_order;                             // [N-1] columns, longest stream first
+  std::vector<ColItem> col_item;                          // every-row form: segments, longest first
+  std::vector<ColJoin> col_join;                          // every-row form: columns in several segments
   std::vector<uint32_t> col_flags;                        // [N-1][colFlagWords(N)] present rows
   int col_split = 0;                                      // column-stream form (see ColRec)
   // Concentration-based, constant-volume Jacobian: species block
@@ -134,6 +150,9 @@ struct MechDev {
   const int* __restrict__ col_start;    // [N]
   const ColRec* __restrict__ colrec;
   const int* __restrict__ col_order;    // [N-1] longest column stream first
+  const ColItem* __restrict__ col_item; // [n_col_item] every-row form, longest first
+  const ColJoin* __restrict__ col_join; // [n_col_join]
+  int n_col_item, n_col_join;
   const uint32_t* __restrict__ col_flags;  // [N-1][colFlagWords(N)]
   const int* __restrict__ cv_col_start;    // [N + 1]
   const ColRec* __restrict__ cv_colrec;
