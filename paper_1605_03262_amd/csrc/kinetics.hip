@@ -9,7 +9,8 @@
 //   persistent : X[N+1] (concentrations, X[N] = 1), KF[NR] = c k_f,
 //                KR[NR] = c k_r, G[NG] = (dc/dE) R, per-state scalars
 //   alias      : phase A  Bk[N], dBk[N], per-species c_p terms [2][N]
-//                phase B  Bk[N], dBk[N], chunk[4][G] of per-reaction results
+//                phase B  Bk[N], dBk[N], chunk[2][4][G] of per-reaction results
+//                         (two buffers used in turn)
 //                phase C+ WA[N], WB[N], JT[N], H[N], per-species sum terms [2][N]
 // Every per-state sum over species is formed by one thread in species order
 // and no atomics are used, so a state's results depend neither on its
@@ -44,13 +45,33 @@ enum { SC_T = 0, SC_IT, SC_LT, SC_P, SC_LP, SC_L10P, SC_RHO, SC_W, SC_M, SC_CP, 
 // per-state scalars of the concentration-based form, in the same rows
 enum { SC_IM = SC_RHO, SC_DEN = SC_CP, SC_SUW = SC_DCP, SC_SUU = SC_SHW };
 
+// Register budget of the tile kernels, as wavefronts per SIMD: 4 (128
+// registers) for 512- and 1024-thread workgroups; 3 (168 registers, no
+// spills at 53 species) for 256-thread ones, whose LDS lets three
+// workgroups share a CU.
+constexpr int tile_waves_per_eu(int nt) { return nt == 256 ? 3 : (nt <= 512 ? 4 : 1); }
+
+// Phase B keeps its per-reaction results in two buffers used in turn (one
+// barrier per reaction chunk instead of two) when the second buffer costs no
+// workgroup per CU: the workgroups a CU holds are the fewer of what its
+// register budget (4 SIMDs) and its 160 KiB of LDS allow.
+__host__ __device__ inline bool two_chunk_buffers(int rows1, int rows2, int TS, int NT) {
+  const int waves = NT / 64;
+  const int by_regs = (4 * (NT == 256 ? 3 : 4)) / waves;
+  const int lds1 = (160 * 1024) / (rows1 * TS * 8), lds2 = (160 * 1024) / (rows2 * TS * 8);
+  const int wg1 = by_regs < lds1 ? by_regs : lds1, wg2 = by_regs < lds2 ? by_regs : lds2;
+  return wg2 >= wg1;
+}
+
 // LDS layout in doubles; each entry counts rows of TS doubles.
 struct TileLayout {
   int X, KF, KR, G, SC, alias;
   int Bk, dBk, chunk, redA;      // phases A/B (alias)
   int WA, WB, JT, H, redC;       // phases C/D (alias)
   int rows;                      // total rows
-  __host__ __device__ TileLayout(int N, int NR, int NG, int Gr, bool jac) {
+  int nbuf;                      // phase-B chunk buffers (1 or 2)
+  __host__ __device__ TileLayout(int N, int NR, int NG, int TS, int NT, bool jac) {
+    const int Gr = NT / TS;
     X = 0;
     KF = X + N + 1;                         // must directly follow X: column streams index both from X
     KR = KF + (jac ? NR : 0);
@@ -61,7 +82,6 @@ struct TileLayout {
     dBk = Bk + N;
     redA = dBk + (jac ? N : 0);             // per-species terms summed in species order
     chunk = redA;                           // phase B reuses the phase-A reduction rows
-    int endB = chunk + (jac ? 4 : 1) * Gr;
     int endA = redA + (jac ? 2 : 1) * N;
     WA = alias;                             // WA and WB interleaved: [k][s][2], k = 0..N (row N: slack)
     WB = WA;
@@ -69,8 +89,13 @@ struct TileLayout {
     H = JT + (jac ? N : 0);                 // k = 0..N (row N: slack)
     redC = H + (jac ? N + 1 : 0);
     int endC = redC + (jac ? 2 : 1) * N;
-    int e = endB > endA ? endB : endA;
-    rows = e > endC ? e : endC;
+    auto total = [&](int nb) {
+      const int endB = chunk + nb * (jac ? 4 : 1) * Gr;
+      const int e = endB > endA ? endB : endA;
+      return e > endC ? e : endC;
+    };
+    nbuf = two_chunk_buffers(total(1), total(2), TS, NT) ? 2 : 1;
+    rows = total(nbuf);
   }
 };
 
@@ -367,7 +392,7 @@ __device__ __forceinline__ void tile_body(const MechDev& md, unsigned tile, int6
   const int64_t sg = (int64_t)tile * TS + s;
   const bool live = sg < n;
   const int64_t sl = live ? sg : n - 1;
-  const TileLayout L(N, NR, NG, Gr, JAC);
+  const TileLayout L(N, NR, NG, TS, NT, JAC);
   double* X = lds + (size_t)L.X * TS + s;
   double* SC = lds + (size_t)L.SC * TS + s;
   double* Bk = lds + (size_t)L.Bk * TS + s;
@@ -451,15 +476,21 @@ __device__ __forceinline__ void tile_body(const MechDev& md, unsigned tile, int6
   __syncthreads();
 
   // ---- phase B: reactions in chunks of Gr, gathered per species (no atomics)
-  double* chunk = lds + (size_t)L.chunk * TS + s;
+  double* const chunk0 = lds + (size_t)L.chunk * TS + s;
   double* KF = lds + (size_t)L.KF * TS + s;
   double* KR = lds + (size_t)L.KR * TS + s;
   double* Gs = lds + (size_t)L.G * TS + s;
   double acc[KPT][4];
 #pragma unroll
   for (int q = 0; q < KPT; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.0;
+  // With two result buffers the chunks alternate between them and one
+  // barrier per chunk suffices: the barrier after chunk c's evaluation also
+  // orders every gather of chunk c - 1 before chunk c + 1 overwrites that
+  // buffer.  With one, a second barrier follows the gathers.
+  const bool two = L.nbuf == 2;
   for (int c0 = 0, ch = 0; c0 < NR; c0 += Gr, ++ch) {
     const int i = c0 + g;
+    double* const chunk = chunk0 + (two ? (ch & 1) : 0) * (JAC ? 4 : 1) * Gr * TS;
     // this chunk's gather bounds and first list entries, fetched before the
     // reaction evaluation so that their latency overlaps it
     const int* bnd = md.spg_chunk + (size_t)ch * N;
@@ -525,8 +556,9 @@ __device__ __forceinline__ void tile_body(const MechDev& md, unsigned tile, int6
         }
       }
     }
-    __syncthreads();
+    if (!two) __syncthreads();
   }
+  if (two) __syncthreads();     // the last gathers, before phase C reuses the rows
 
   // ---- phase C: species terms, RHS (Eqs. ode, dTdt), J[0][0] sums
   double2* WAB = reinterpret_cast<double2*>(lds + (size_t)L.WA * TS) + s;
@@ -785,12 +817,6 @@ __device__ __forceinline__ void tile_body(const MechDev& md, unsigned tile, int6
   }
 }
 
-// Register budget of the tile kernels, as wavefronts per SIMD: 4 (128
-// registers) for 512- and 1024-thread workgroups; 3 (168 registers, no
-// spills at 53 species) for 256-thread ones, whose LDS lets three
-// workgroups share a CU.
-constexpr int tile_waves_per_eu(int nt) { return nt == 256 ? 3 : (nt <= 512 ? 4 : 1); }
-
 template <int TS, int NT, int KPT, bool JAC, bool SPLIT>
 __global__ __launch_bounds__(NT, tile_waves_per_eu(NT)) void tile_kernel(MechDev md, int64_t n, int64_t ld,
                                                   const double* __restrict__ phi,
@@ -830,8 +856,9 @@ __global__ __launch_bounds__(NT, tile_waves_per_eu(NT)) void tile_multi_kernel(W
 // The tile mapping and the reaction phase are those of tile_kernel; phase D
 // streams only the rows with terms and stores each once.
 struct CvLayout {
-  int X, KF, KR, G, SC, alias, Bk, dBk, chunk, H, red, rows;
-  __host__ __device__ CvLayout(int N, int NR, int NG, int Gr) {
+  int X, KF, KR, G, SC, alias, Bk, dBk, chunk, H, red, rows, nbuf;
+  __host__ __device__ CvLayout(int N, int NR, int NG, int TS, int NT) {
+    const int Gr = NT / TS;
     X = 0;
     KF = X + N + 1;
     KR = KF + NR;
@@ -843,8 +870,13 @@ struct CvLayout {
     chunk = dBk + N;
     H = alias;                          // phases C, D: U_k (row N: slack)
     red = H + N + 1;                    // five per-species sum terms [5][N]
-    const int endB = chunk + 4 * Gr, endC = red + 5 * N;
-    rows = endB > endC ? endB : endC;
+    const int endC = red + 5 * N;
+    auto total = [&](int nb) {
+      const int endB = chunk + nb * 4 * Gr;
+      return endB > endC ? endB : endC;
+    };
+    nbuf = two_chunk_buffers(total(1), total(2), TS, NT) ? 2 : 1;   // as TileLayout
+    rows = total(nbuf);
   }
 };
 
@@ -859,7 +891,7 @@ __global__ __launch_bounds__(NT, tile_waves_per_eu(NT)) void conc_tile_kernel(Me
   const int64_t sg = (int64_t)xcd_tile() * TS + s;
   const bool live = sg < n;
   const int64_t sl = live ? sg : n - 1;
-  const CvLayout L(N, NR, NG, Gr);
+  const CvLayout L(N, NR, NG, TS, NT);
   double* X = lds + (size_t)L.X * TS + s;
   double* SC = lds + (size_t)L.SC * TS + s;
   double* Bk = lds + (size_t)L.Bk * TS + s;
@@ -904,15 +936,18 @@ __global__ __launch_bounds__(NT, tile_waves_per_eu(NT)) void conc_tile_kernel(Me
 
   // ---- phase B: reactions in chunks, gathered per species (no atomics):
   // acc 0 wdot_k, 1 d wdot_k/dT, 2 u_k
-  double* chunk = lds + (size_t)L.chunk * TS + s;
+  double* const chunk0 = lds + (size_t)L.chunk * TS + s;
   double* KF = lds + (size_t)L.KF * TS + s;
   double* KR = lds + (size_t)L.KR * TS + s;
   double* Gs = lds + (size_t)L.G * TS + s;
   double acc[KPT][3];
 #pragma unroll
   for (int q = 0; q < KPT; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
+  // one or two result buffers, as in tile_body
+  const bool two = L.nbuf == 2;
   for (int c0 = 0, ch = 0; c0 < NR; c0 += Gr, ++ch) {
     const int i = c0 + g;
+    double* const chunk = chunk0 + (two ? (ch & 1) : 0) * 4 * Gr * TS;
     const int* bnd = md.spg_chunk + (size_t)ch * N;
     int gb0[KPT], gb1[KPT];
 #pragma unroll
@@ -963,8 +998,9 @@ __global__ __launch_bounds__(NT, tile_waves_per_eu(NT)) void conc_tile_kernel(Me
         }
       }
     }
-    __syncthreads();
+    if (!two) __syncthreads();
   }
+  if (two) __syncthreads();     // the last gathers, before phase C reuses the rows
 
   // ---- phase C: temperature column, dense row parts, temperature-row sums
   double* H = lds + (size_t)L.H * TS + s;
@@ -1142,7 +1178,7 @@ hipError_t launch_mix_pairs(const MechDev& md, int64_t n, int64_t ld, const doub
 
 // ------------------------------------------------------------------ launchers
 size_t tile_lds_bytes(int N, int NR, int NG, int TS, int NT, bool jac) {
-  TileLayout L(N, NR, NG, NT / TS, jac);
+  TileLayout L(N, NR, NG, TS, NT, jac);
   return (size_t)L.rows * TS * sizeof(double);
 }
 
@@ -1170,7 +1206,7 @@ static hipError_t launch_k(int kpt, const MechDev& md, int64_t n, int64_t ld, co
 }
 
 size_t conc_lds_bytes(int N, int NR, int NG, int TS, int NT) {
-  CvLayout L(N, NR, NG, NT / TS);
+  CvLayout L(N, NR, NG, TS, NT);
   return (size_t)L.rows * TS * sizeof(double);
 }
 
