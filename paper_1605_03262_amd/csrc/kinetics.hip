@@ -672,16 +672,9 @@ __device__ __forceinline__ void tile_body(const MechDev& md, unsigned tile, int6
       double val = wab[0].x * vj + wab[0].y;
       double hk = hp[0];
       double2 abn = wab[TS];
-      ColRec r[kColBatch];
-#pragma unroll
-      for (int u = 0; u < kColBatch; ++u) r[u] = rec[u];
-      for (int b = 0; b < cnt; b += kColBatch) {
-        // the table carries one batch of slack, so the next batch is always readable
-        ColRec nx[kColBatch];
-#pragma unroll
-        for (int u = 0; u < kColBatch; ++u) nx[u] = rec[b + kColBatch + u];
-        // the batch's products first, with no branch between them, so that all
-        // their LDS reads are in flight together; then the row bookkeeping
+      // one batch: the products first, with no branch between them, so that
+      // all their LDS reads are in flight together; then the row bookkeeping
+      auto batch = [&](const ColRec (&r)[kColBatch]) {
         double t[kColBatch];
 #pragma unroll
         for (int u = 0; u < kColBatch; ++u) {
@@ -702,9 +695,24 @@ __device__ __forceinline__ void tile_body(const MechDev& md, unsigned tile, int6
             abn = wab[TS];
           }
         }
+      };
+      // Two record buffers in turn, each batch's loads issued one batch of
+      // work ahead, then a last single batch when the count is odd.  Every
+      // load stays inside the table: a segment is followed by another
+      // segment or by the table's batch of slack.
+      ColRec ra[kColBatch], rb[kColBatch];
 #pragma unroll
-        for (int u = 0; u < kColBatch; ++u) r[u] = nx[u];
+      for (int u = 0; u < kColBatch; ++u) ra[u] = rec[u];
+      int b = 0;
+      for (; b + 2 * kColBatch <= cnt; b += 2 * kColBatch) {
+#pragma unroll
+        for (int u = 0; u < kColBatch; ++u) rb[u] = rec[b + kColBatch + u];
+        batch(ra);
+#pragma unroll
+        for (int u = 0; u < kColBatch; ++u) ra[u] = rec[b + 2 * kColBatch + u];
+        batch(rb);
       }
+      if (b < cnt) batch(ra);
       // the placeholder row N - 1 (not stored) ends the column's last segment;
       // after an earlier segment the open row belongs to the next one
       if (I.last) TR += hk * val;
