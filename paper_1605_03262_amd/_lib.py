@@ -52,6 +52,15 @@ def load_library() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_1605_03262_amd/build.py "
                           "(there is no fallback implementation)")
+    # torch carries its own HIP runtime beside the one this library links; the
+    # process works when torch's is initialised first, so that happens here,
+    # before the library's first HIP call
+    try:
+        import torch
+    except ImportError:
+        torch = None
+    if torch is not None and torch.cuda.is_available():
+        torch.cuda.init()
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     st = ctypes.c_int32

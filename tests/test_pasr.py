@@ -70,7 +70,10 @@ def test_pasr_states_and_jacobian_parity(torch, Ref, cfg, n_res, tau_res):
     reactor = PaSR(M, n_reactors=4, fresh=fresh, pilot=pilot, p_pa=p_pa, tau_res=tau_res, seed=5 + cfg)
     phi, p = reactor.run(n_res)
     assert np.all(np.isfinite(phi))
-    assert np.all(phi[0] > 200.0) and np.all(phi[0] < 5000.0)
+    # the driver's own physical range: the pilot stream is the fresh mixture
+    # at 2000 K (its stiffness stops burn() at the first step), and an unmixed
+    # pilot particle burns adiabatically to about 5200 K at this pressure
+    assert np.all(phi[0] > 200.0) and np.all(phi[0] < 6000.0)
     # the driver keeps steps whose mass fractions lie within 1e-6 of [0, 1]
     # (implicit steps leave rounding-level negatives; they stay in the set,
     # since they are states such integrators hand to the Jacobian)
