@@ -171,9 +171,12 @@ class PaSR:
 
 
 def burn(mech: Mechanism, comp, p_pa: float, t_end: float = 0.05, n_steps: int = 400, h0: float = 1e-8):
-    """Constant-pressure adiabatic evolution of one composition to (near)
+    """Constant-pressure adiabatic evolution of one composition toward
     equilibrium: implicit steps with geometrically growing size from h0 up to
-    t_end (the pilot stream of the premixed PaSR, App. C)."""
+    t_end (the pilot stream of the premixed PaSR, App. C).  It stops at the
+    first step that gives a non-finite state and returns the state reached:
+    for a start too stiff for h0 that is the input itself, which then burns
+    inside the reactor under the particles' step control."""
     torch = _torch()
     phi = torch.from_numpy(np.asarray(comp, dtype=np.float64)[:, None].copy()).cuda()
     p = torch.full((1,), float(p_pa), dtype=torch.float64, device="cuda")
