@@ -677,6 +677,19 @@ def main() -> int:
                                "FP64 otherwise), triangular solves, FP64 residual refinement; non-converging "
                                "states re-solved in FP64")
     log("Newton timed")
+    # the step's other kernel against the same HBM roofline: the mixed solve
+    # reads J once for the FP32 factor and once per refinement sweep (it does
+    # not fit on chip beside the factor), reads b and h, writes x and info
+    mx = newton_info["conditioned_h"]["fp32_lu_fp64_refine"]
+    sweeps = mx.get("refine_sweeps_mean") or 0.0
+    nbytes = n * (8.0 * N * N * (1.0 + sweeps) + 16.0 * N + 12.0)
+    newton_gbs = nbytes / (mx["ms_median"] * 1e-3) / 1e9
+    roofline_newton = {"bound": "hbm", "achieved": newton_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": newton_gbs / HBM_PEAK_GBS,
+                       "kernel": "mixed Newton solve call (conditioned h)", "avg_launch_ms": mx["ms_median"],
+                       "algorithmic_bytes_per_launch": nbytes,
+                       "bytes_per_state": "8 N^2 (1 + mean refinement sweeps) + 16 N + 12",
+                       "refine_sweeps_mean": sweeps}
     rates_info = rates_leg(M, d_phi, d_p, n, N, torch)
     log("rates timed")
     conc_info = conc_leg(M, mech, phi, p, torch)
@@ -708,6 +721,7 @@ def main() -> int:
                      "target_frac": 0.60,
                      "measured_write_peak_GBps": stream_write_gbs,
                      "frac_of_measured_write_peak": achieved / stream_write_gbs},
+        "roofline_newton": roofline_newton,
         "parity_sample": parity,
         "newton": newton_info,
         "rates": rates_info,
