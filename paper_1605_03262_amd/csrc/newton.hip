@@ -550,9 +550,19 @@ __global__ void small_compact_kernel(int64_t n, const int* __restrict__ info, in
 // row, ties going to the lower row; the pivot row travels through LDS.  The
 // residual r = b - (I - h gamma J) x is formed in FP64 from the FP64 Jacobian
 // in memory at every sweep (the FP64 matrix does not fit beside the factor).
-constexpr int kGrpWaves = 4;   // wavefronts per workgroup
+constexpr int kGrpWaves = 2;   // wavefronts per workgroup
 constexpr int kGrpOcc = 2;     // wavefronts per SIMD the register budget is sized for
-constexpr int kGrpStage = 128; // staged Jacobian rows x states per workgroup
+// LDS stage of Jacobian rows per workgroup: with the static buffers, four
+// workgroups (eight wavefronts, the register limit) fit a CU's 160 KiB
+constexpr int kGrpStageBytes = 32768;
+
+// Jacobian rows per staging pass: as many whole rows of the workgroup's WS
+// states as the stage holds, at most N.  Every row's residual is one dot
+// product in column order, so the pass size does not change any result.
+__host__ __device__ inline int grp_stage_rows(int N, int WS) {
+  const int r = kGrpStageBytes / (N * WS * (int)sizeof(double));
+  return r < 1 ? 1 : (r > N ? N : r);
+}
 
 template <int G>
 __device__ __forceinline__ unsigned group_max_u32(unsigned v) {
@@ -672,7 +682,7 @@ __device__ __forceinline__ void grp_stage(int N, int64_t ld, const double* __res
 // Workgroup of kGrpWaves wavefronts, WS = kGrpWaves * S states.  info: sweep
 // count, ST_SING32 (zero or non-finite FP32 pivot column), ST_UNSET (no
 // convergence within max_refine sweeps) or -3 (non-finite input); the last
-// three are left for the FP64 fallback.  Dynamic LDS: the stage of SRB
+// three are left for the FP64 fallback.  Dynamic LDS: the stage of srb
 // Jacobian rows (grp_lds_bytes).
 template <int NC, int S>
 __global__ __launch_bounds__(kGrpWaves * 64, kGrpOcc) void grp_mixed_kernel(int N, int64_t n, int64_t ld,
@@ -681,9 +691,10 @@ __global__ __launch_bounds__(kGrpWaves * 64, kGrpOcc) void grp_mixed_kernel(int 
                                                                     const double* __restrict__ rhs,
                                                                     double* __restrict__ x, int* __restrict__ info,
                                                                     int max_refine, double rtol) {
-  constexpr int G = 64 / S, R = S, WS = kGrpWaves * S, SRB = kGrpStage / WS;
+  constexpr int G = 64 / S, R = S, WS = kGrpWaves * S;
+  const int srb = grp_stage_rows(N, WS);
   static_assert(NC % 4 == 0 && NC <= 64, "column count");
-  extern __shared__ double stage[];                        // SRB * N * WS
+  extern __shared__ double stage[];                        // srb * N * WS
   __shared__ __align__(16) float pbuf[kGrpWaves][S][NC];   // pivot row of the current step
   __shared__ int pvbuf[kGrpWaves][S][64];                  // pivot row of each step
   __shared__ float obuf[kGrpWaves][S][64];                 // FP32 solutions
@@ -722,8 +733,8 @@ __global__ __launch_bounds__(kGrpWaves * 64, kGrpOcc) void grp_mixed_kernel(int 
     stp[r] = used[r] ? 64 : -1;
     sfor<0, NC>([&](auto j) { a[r][j] = (!used[r] && i >= N && i == j) ? 1.0f : 0.0f; });
   });
-  for (int i0 = 0; i0 < N; i0 += SRB) {
-    const int rows = min(SRB, N - i0);
+  for (int i0 = 0; i0 < N; i0 += srb) {
+    const int rows = min(srb, N - i0);
     grp_stage<WS>(N, ld, jac, sst, dma, i0, rows, stage);
     __syncthreads();
     sfor<0, R>([&](auto r) {
@@ -819,8 +830,8 @@ __global__ __launch_bounds__(kGrpWaves * 64, kGrpOcc) void grp_mixed_kernel(int 
     if (!__syncthreads_or(!done)) break;          // uniform over the workgroup (it stages together)
     float c[R];
     sfor<0, R>([&](auto r) { c[r] = 0.0f; });
-    for (int i0 = 0; i0 < N; i0 += SRB) {
-      const int rows = min(SRB, N - i0);
+    for (int i0 = 0; i0 < N; i0 += srb) {
+      const int rows = min(srb, N - i0);
       grp_stage<WS>(N, ld, jac, sst, dma, i0, rows, stage);
       __syncthreads();
       sfor<0, R>([&](auto r) {
@@ -870,10 +881,10 @@ __global__ __launch_bounds__(kGrpWaves * 64, kGrpOcc) void grp_mixed_kernel(int 
     });
 }
 
-// stage of SRB Jacobian rows
+// stage of grp_stage_rows Jacobian rows
 size_t grp_lds_bytes(int N, int S) {
   const size_t WS = (size_t)kGrpWaves * S;
-  return (size_t)(kGrpStage / WS) * N * WS * sizeof(double);
+  return (size_t)grp_stage_rows(N, (int)WS) * N * WS * sizeof(double);
 }
 
 // the SW x NM solution buffer + the stage + SW x NM slack for the reads
